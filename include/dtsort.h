@@ -1,0 +1,202 @@
+/*
+ * dtsort.h -- C ABI of an MI355X (gfx950) implementation of DovetailSort, the
+ * stable parallel MSD integer sort of "Parallel Integer Sort: Theory and
+ * Practice" (Dong, Dhulipala, Gu, Sun; PPoPP 2024).
+ *
+ * Problem (Section 2.3): given n records with integer keys in [r], reorder them
+ * so that keys are non-decreasing.  The sort is stable (equal keys keep their
+ * input order; Section 2.3), and, as in the paper, the interface is "in place"
+ * (the sorted result replaces the input) while O(n) extra space is used.
+ *
+ * Method (Alg. 2, Sections 3.1-3.5 and 5): per recursive subproblem, sample
+ * keys to find heavy (frequently repeated) keys and the key range, give every
+ * MSD zone one light bucket followed by its heavy buckets, stable-distribute
+ * by bucket id (a counting sort), recurse only into light buckets (heavy
+ * buckets are finished), then interleave each zone's sorted light run with its
+ * heavy runs (the dovetail merge, Alg. 3).  Small subproblems are sorted in
+ * the GPU's local data share; subproblems of one recursion level are processed
+ * together in shared launches.
+ *
+ * Conventions for every entry point:
+ *  - Data pointers are DEVICE pointers owned by the caller.  Keys (and values)
+ *    are sorted in place.  Keys are unsigned integers.
+ *  - `stream` is a hipStream_t (NULL = the null stream).  Work is enqueued on
+ *    it.  The sorts read back one small block of counters per recursion level
+ *    (a synchronisation of `stream`) to size the next level's launches; the
+ *    last level's leaf sorts and the dovetail merges are left enqueued, so the
+ *    caller synchronises `stream` before reading the result.
+ *  - Temporary device memory (a ping-pong partner of the data plus small
+ *    per-level tables) is taken from a per-device cache that grows as needed
+ *    and is kept until dtsort_release() or process exit; or, for the large
+ *    partner buffer, from opts->workspace when the caller supplies one.
+ *    Calls on one device are serialised (each call waits for the previous
+ *    call's work before reusing the cache).
+ *  - Return value: DTSORT_OK or a negative dtsort_status.  No exception ever
+ *    crosses this interface.  On error nothing is guaranteed about the data
+ *    except that no memory outside the given arrays is written.
+ *  - n = 0 and n = 1 are valid no-ops.  n must be < 2^32.
+ */
+#ifndef DTSORT_H
+#define DTSORT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum dtsort_status {
+  DTSORT_OK = 0,
+  DTSORT_EINVAL = -1,     /* bad argument (NULL with n > 0, n >= 2^32, overlap, bad offsets) */
+  DTSORT_ENOMEM = -2,     /* device allocation failed */
+  DTSORT_EWORKSPACE = -3, /* opts->workspace given but smaller than dtsort_workspace_bytes() */
+  DTSORT_EHIP = -4,       /* a HIP runtime call failed (message via dtsort_last_error()) */
+  DTSORT_EINTERNAL = -5   /* a device-side capacity or consistency check failed */
+} dtsort_status;
+
+typedef enum dtsort_mode {
+  DTSORT_MODE_SAMPLING = 0, /* the paper's method: heavy keys found by sampling (Section 3.1) */
+  DTSORT_MODE_PLAIN = 1,    /* heavy-key detection off: the paper's "Plain" ablation (Section 6.3) */
+  DTSORT_MODE_LEARNED = 2   /* root zones from a learned CDF model's splitters, sampling as fallback/judge */
+} dtsort_mode;
+
+/* Counters filled when opts->stats is non-NULL (host memory; valid after the
+ * call returns -- they are read back during the call). */
+typedef struct dtsort_stats {
+  uint64_t levels;              /* recursion levels that distributed records */
+  uint64_t tasks;               /* subproblems distributed (sampling + counting sort) */
+  uint64_t records_distributed; /* sum of their sizes */
+  uint64_t heavy_keys;          /* heavy keys found (all levels) */
+  uint64_t heavy_records;       /* records in heavy buckets */
+  uint64_t merges;              /* zones dovetail-merged */
+  uint64_t records_merged;      /* records written by dovetail merges */
+  uint64_t leaf_sorts;          /* local-memory base-case sorts */
+  uint64_t records_leaf_sorted; /* records they sorted */
+  uint64_t records_copied;      /* records moved between buffers (finished buckets, spills) */
+  uint64_t overflow_records;    /* records that landed in overflow buckets */
+  int32_t learned_used;         /* LEARNED mode: 1 if the model's zones were used */
+  float learned_balance;        /* LEARNED mode: balance error of the model's zones */
+  float sampling_balance;       /* LEARNED mode: balance error of the digit zones */
+  float learned_final_loss;     /* LEARNED mode: training loss of the last step */
+  double learned_ms;            /* LEARNED mode: time spent training + judging (ms) */
+} dtsort_stats;
+
+typedef struct dtsort_opts {
+  uint64_t seed;          /* seed of the sampling generator (Appendix A: deterministic given it) */
+  int32_t key_bits;       /* 0 = full width; else keys are < 2^key_bits (the paper's optional bit count) */
+  int32_t mode;           /* dtsort_mode */
+  int32_t digit_bits;     /* 0 = automatic (log2 of the cube root of n', clamped to [8, 11]); else 1..11 */
+  int32_t lds_cutoff;     /* 0 = automatic; base-case threshold theta (records) */
+  int32_t tuned;          /* 1 = take digit_bits / lds_cutoff from the autotuner's table when they are 0 */
+  int32_t learned_steps;  /* LEARNED: optimiser steps (0 = default 512) */
+  int32_t learned_batch;  /* LEARNED: batch size (0 = default 1024) */
+  float learned_lr;       /* LEARNED: Adam step size (0 = default 3e-3) */
+  void* workspace;        /* optional device buffer for the ping-pong partner (see dtsort_workspace_bytes) */
+  size_t workspace_bytes;
+  dtsort_stats* stats;    /* optional host pointer */
+} dtsort_opts;
+
+/* Fill *opts with defaults (seed 0, automatic parameters, SAMPLING mode). */
+void dtsort_default_opts(dtsort_opts* opts);
+
+/* Bytes of caller-supplied workspace needed for n records of key_bytes-wide
+ * keys and val_bytes-wide values (0 for keys only): the ping-pong partner of
+ * the data (Section 5, "minimizing data movement"), rounded to 256 bytes. */
+size_t dtsort_workspace_bytes(int key_bytes, int val_bytes, size_t n);
+
+/* Stable ascending sort of n 32-bit keys in place. */
+int dtsort_u32(uint32_t* keys, size_t n, const dtsort_opts* opts, void* stream);
+
+/* Stable ascending sort of n 64-bit keys in place. */
+int dtsort_u64(uint64_t* keys, size_t n, const dtsort_opts* opts, void* stream);
+
+/* Stable sort of n (64-bit key, 64-bit value) records stored as two arrays
+ * (structure of arrays); values move with their keys.  keys and values must
+ * not overlap. */
+int dtsort_pairs_u64(uint64_t* keys, uint64_t* values, size_t n, const dtsort_opts* opts, void* stream);
+
+/* Batched form: n_segments independent stable sorts of 32-bit keys (and
+ * optional 32-bit values, NULL for keys only) stored back to back.  Segment s
+ * is [seg_offsets[s], seg_offsets[s+1]); seg_offsets is a DEVICE array of
+ * n_segments + 1 uint64 with seg_offsets[0] = 0, non-decreasing and
+ * seg_offsets[n_segments] = n_total (checked on the device; a violation
+ * returns DTSORT_EINVAL).  Empty segments are allowed.  All segments are
+ * processed level by level in shared launches. */
+int dtsort_segmented(uint32_t* keys, uint32_t* values, size_t n_total, const uint64_t* seg_offsets,
+                     size_t n_segments, const dtsort_opts* opts, void* stream);
+
+/* ---- step entry points: one step of the method on one subproblem, for
+ * step-level checks against a CPU model.  Same conventions as above; they
+ * synchronise `stream` before returning. ---- */
+
+/* Step 1 (Section 3.1 and the sampled key range of Section 5) on the n keys,
+ * as the root subproblem (offset 0, level 0) whose keys share all bits at and
+ * above `hi`.  Outputs (host pointers): plan[0..5] = {gamma, w, shift, top,
+ * n_heavy, n_buckets}; heavy[0..n_heavy) = heavy keys ascending (room for
+ * 1024 entries); light_id[0..2^w] = the light bucket id of each zone (the last
+ * entry is the overflow bucket id; room for 2049 entries). */
+int dtsort_step_plan_u32(const uint32_t* keys, size_t n, int hi, int skip_disabled, const dtsort_opts* opts,
+                         int32_t* plan, uint32_t* heavy, uint32_t* light_id, void* stream);
+int dtsort_step_plan_u64(const uint64_t* keys, size_t n, int hi, int skip_disabled, const dtsort_opts* opts,
+                         int32_t* plan, uint64_t* heavy, uint32_t* light_id, void* stream);
+
+/* Steps 1 + 2 (Section 3.2, the stable counting sort by GetBucketId) on the
+ * root subproblem: keys (and values, may be NULL) are distributed into
+ * out_keys / out_values (device, n each); counts (host, room for 4097) gets
+ * the record count of every bucket id; plan/heavy/light_id as above. */
+int dtsort_step_distribute_u32(const uint32_t* keys, const uint32_t* values, size_t n, int hi,
+                               const dtsort_opts* opts, uint32_t* out_keys, uint32_t* out_values,
+                               uint32_t* counts, int32_t* plan, uint32_t* heavy, uint32_t* light_id,
+                               void* stream);
+int dtsort_step_distribute_u64(const uint64_t* keys, const uint64_t* values, size_t n, int hi,
+                               const dtsort_opts* opts, uint64_t* out_keys, uint64_t* out_values,
+                               uint32_t* counts, int32_t* plan, uint64_t* heavy, uint32_t* light_id,
+                               void* stream);
+
+/* Base case (Section 3.5): stable local-memory sort of each segment
+ * [seg_offsets[s], seg_offsets[s+1]) (device array) of at most 16384 keys
+ * (8192 for 64-bit pairs) by the key bits below `bits`; out-of-place into
+ * out_keys/out_values. */
+int dtsort_step_leaf_u32(const uint32_t* keys, const uint32_t* values, const uint64_t* seg_offsets,
+                         size_t n_segments, int bits, uint32_t* out_keys, uint32_t* out_values, void* stream);
+int dtsort_step_leaf_u64(const uint64_t* keys, const uint64_t* values, const uint64_t* seg_offsets,
+                         size_t n_segments, int bits, uint64_t* out_keys, uint64_t* out_values, void* stream);
+
+/* Step 4 (Section 3.4, Alg. 3) on one MSD zone: b0 sorted light records
+ * (b0_keys/b0_values, device) and m heavy buckets given by host arrays
+ * heavy_keys[m] (ascending, none equal to a light key) and heavy_sizes[m];
+ * heavy values (device, sum of sizes, bucket after bucket; NULL for keys
+ * only).  Writes the merged zone to out_keys / out_values (device). */
+int dtsort_step_dtmerge_u64(const uint64_t* b0_keys, const uint64_t* b0_values, size_t b0,
+                            const uint64_t* heavy_keys, const uint32_t* heavy_sizes, size_t m,
+                            const uint64_t* heavy_values, uint64_t* out_keys, uint64_t* out_values,
+                            void* stream);
+
+/* ---- learned partitioner (not in the paper): FP32 CDF model 1->64->64->1 ----
+ * Parameters are 4353 floats in the order W1[64], b1[64], W2[64][64] (row =
+ * output unit), b2[64], W3[64], b3.  All pointers are device pointers. */
+
+/* Mean squared error of the model on (x[i], y[i]), i < n, and its gradient
+ * (4353 floats, overwritten); loss is one float. */
+int dtsort_mlp_loss_grad(const float* params, const float* x, const float* y, size_t n, float* grad,
+                         float* loss, void* stream);
+/* Forward pass: pred[i] = model(x[i]). */
+int dtsort_mlp_forward(const float* params, const float* x, size_t n, float* pred, void* stream);
+/* Train from the deterministic initialisation of `seed` on sorted keys
+ * (64-bit, device, n of them) for `steps` Adam steps; writes params (4353
+ * floats) and losses[steps] (may be NULL). */
+int dtsort_mlp_train_u64(const uint64_t* sorted_keys, size_t n, uint64_t seed, int steps, int batch,
+                         float lr, float* params, float* losses, void* stream);
+
+/* Release the per-device cache (call with no sort in flight). */
+void dtsort_release(void);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char* dtsort_last_error(void);
+const char* dtsort_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DTSORT_H */

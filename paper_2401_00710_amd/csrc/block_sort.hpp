@@ -1,0 +1,145 @@
+// Stable LSD radix sort of up to THREADS*ITEMS keys held in registers, using
+// LDS for the exchange.  Used for the sample sort of the sampling step
+// (Section 3.1) and for the base-case sort of small subproblems (Section 3.5),
+// which must be stable for the whole method to be stable.
+//
+// Layout: thread (wave w, lane l) holds items i = 0..ITEMS-1 at element index
+// w*64*ITEMS + i*64 + l ("wave-striped": every item load of a wave is one
+// contiguous 64-element row).  Each 8-bit pass ranks keys with a wave-wide
+// ballot match (peers with the same digit, counted below the lane), keeps a
+// running count per (wave, digit) in LDS, and turns the counts into offsets by
+// an exclusive scan in (digit, wave) order.  Processing items in order i and
+// lanes in order l visits elements in index order, so equal digits keep their
+// order: the pass is stable.
+#pragma once
+#include "common.hpp"
+
+namespace dts {
+
+template <int THREADS, int ITEMS>
+__device__ inline int striped_index(int i) {
+  return (threadIdx.x / WAVE) * WAVE * ITEMS + i * WAVE + (threadIdx.x & (WAVE - 1));
+}
+
+// LDS words (u32) needed for the counters of block_radix_sort.
+template <int THREADS>
+constexpr int bsort_cnt_words() {
+  return (THREADS / WAVE) * 256 + THREADS / WAVE + 1;
+}
+
+// Sorts k[] (and carries ix[] when IDX) by key bits [lo_bit, hi_bit).
+// sk: LDS array of THREADS*ITEMS keys; si: LDS array of THREADS*ITEMS u16
+// (only when IDX); cnt: bsort_cnt_words<THREADS>() u32.  On return k[]/ix[]
+// hold the sorted sequence in the striped layout and sk (si) holds it in order.
+template <typename K, int THREADS, int ITEMS, bool IDX>
+__device__ void block_radix_sort(K (&k)[ITEMS], uint16_t (&ix)[ITEMS], int lo_bit, int hi_bit, K* sk,
+                                 uint16_t* si, uint32_t* cnt) {
+  constexpr int WAVES = THREADS / WAVE;
+  static_assert(THREADS >= 256, "one thread per digit in the scan");
+  const int wv = threadIdx.x / WAVE;
+  uint32_t* tmp = cnt + WAVES * 256;
+  for (int bit = lo_bit; bit < hi_bit; bit += 8) {
+    const int nbits = min(8, hi_bit - bit);
+    const uint32_t dmask = (1u << nbits) - 1u;
+    for (int i = threadIdx.x; i < WAVES * 256; i += THREADS) cnt[i] = 0;
+    __syncthreads();
+    uint32_t* wc = cnt + wv * 256;
+    uint32_t pos[ITEMS];
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+      const uint32_t d = (uint32_t)(shr<K>(k[i], bit)) & dmask;
+      const uint64_t peers = match_peers(d, nbits, true);
+      const uint32_t r = mbcnt(peers);
+      const uint32_t c = (uint32_t)__popcll(peers);
+      const uint32_t base = wc[d];
+      pos[i] = base + r;
+      if (r == 0) wc[d] = base + c;
+    }
+    __syncthreads();
+    // exclusive offsets in (digit, wave) order
+    const int t = threadIdx.x;
+    uint32_t s = 0;
+    if (t < 256) {
+      for (int w = 0; w < WAVES; ++w) s += cnt[w * 256 + t];
+    }
+    uint32_t total;
+    uint32_t run = block_excl_scan<THREADS>(t < 256 ? s : 0u, tmp, &total);
+    if (t < 256) {
+      for (int w = 0; w < WAVES; ++w) {
+        const uint32_t c = cnt[w * 256 + t];
+        cnt[w * 256 + t] = run;
+        run += c;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+      const uint32_t d = (uint32_t)(shr<K>(k[i], bit)) & dmask;
+      const uint32_t p = pos[i] + wc[d];
+      sk[p] = k[i];
+      if constexpr (IDX) si[p] = ix[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+      const int e = striped_index<THREADS, ITEMS>(i);
+      k[i] = sk[e];
+      if constexpr (IDX) ix[i] = si[e];
+    }
+    __syncthreads();
+  }
+}
+
+// Bitwise OR and AND of the first n elements held in k[] (striped layout),
+// reduced over the workgroup.  red: LDS of 2*(THREADS/64) K.
+template <typename K, int THREADS, int ITEMS>
+__device__ inline void block_or_and(const K (&k)[ITEMS], int n, K* red, K* out_or, K* out_and) {
+  constexpr int WAVES = THREADS / WAVE;
+  K o = 0, a = ~(K)0;
+#pragma unroll
+  for (int i = 0; i < ITEMS; ++i) {
+    if (striped_index<THREADS, ITEMS>(i) < n) {
+      o |= k[i];
+      a &= k[i];
+    }
+  }
+#pragma unroll
+  for (int off = WAVE / 2; off > 0; off >>= 1) {
+    o |= __shfl_xor(o, off, WAVE);
+    a &= __shfl_xor(a, off, WAVE);
+  }
+  const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+  if (lane == 0) {
+    red[wv] = o;
+    red[WAVES + wv] = a;
+  }
+  __syncthreads();
+  K ro = 0, ra = ~(K)0;
+  for (int w = 0; w < WAVES; ++w) {
+    ro |= red[w];
+    ra &= red[WAVES + w];
+  }
+  *out_or = ro;
+  *out_and = ra;
+  __syncthreads();
+}
+
+template <typename K>
+__device__ inline int bit_length(K x) {
+  if constexpr (sizeof(K) == 8) {
+    return x ? 64 - __builtin_clzll((unsigned long long)x) : 0;
+  } else {
+    return x ? 32 - __builtin_clz((unsigned)x) : 0;
+  }
+}
+
+template <typename K>
+__device__ inline int trailing_zeros(K x) {
+  if constexpr (sizeof(K) == 8) {
+    return x ? __builtin_ctzll((unsigned long long)x) : 64;
+  } else {
+    return x ? __builtin_ctz((unsigned)x) : 32;
+  }
+}
+
+}  // namespace dts

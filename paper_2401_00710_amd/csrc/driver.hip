@@ -1,0 +1,490 @@
+// Host driver of the DovetailSort library: the level loop of Alg. 2 over
+// batched subproblems, device memory management, and the C ABI of dtsort.h.
+//
+// Per level: prep (chunking) -> plan (Step 1) -> histogram, column scan,
+// bucket scan, scatter (Step 2) -> child planning (Step 3 bookkeeping) ->
+// read back one block of counters -> leaf sorts and copies of this level.
+// After the last level the dovetail merges (Step 4) run deepest level first,
+// so every zone merges after its light bucket is completely sorted.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/dtsort.h"
+#include "launch.hpp"
+
+namespace dts {
+
+static thread_local std::string g_err;
+
+static int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHK(x)                                                                          \
+  do {                                                                                     \
+    hipError_t e_ = (x);                                                                   \
+    if (e_ != hipSuccess) return fail(DTSORT_EHIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+};
+
+constexpr int MAX_LEVELS = 160;
+
+struct LevelKeep {
+  DevBuf tab, merges, munits, spills;
+  uint32_t n_merges = 0, n_munits = 0, n_spills = 0;
+};
+
+struct Ctx {
+  int device = -1;
+  DevBuf tk, tv;                 // ping-pong partner of keys / values
+  DevBuf tasks[2], units, cm, leaf[3], copies, ctr, scratch;
+  std::vector<LevelKeep> lv;
+  LevelCounters* h_ctr = nullptr;  // pinned
+  void* h_stage = nullptr;         // pinned staging (task upload etc.)
+  hipEvent_t done = nullptr;
+  hipStream_t last_stream = nullptr;
+  bool has_last = false;
+};
+
+static std::mutex g_mu;
+static std::vector<Ctx*> g_ctx;
+
+// Grow-only device buffer; synchronises `s` first when it must reallocate,
+// since earlier enqueued work may still use the old allocation.
+static int ensure(DevBuf& b, size_t bytes, hipStream_t s) {
+  if (bytes == 0) bytes = 64;
+  if (b.cap >= bytes) return 0;
+  HIPCHK(hipStreamSynchronize(s));
+  if (b.p) HIPCHK(hipFree(b.p));
+  b.p = nullptr;
+  b.cap = 0;
+  size_t want = std::max(bytes, b.cap + b.cap / 2);
+  want = (want + 255) & ~(size_t)255;
+  if (hipMalloc(&b.p, want) != hipSuccess) {
+    (void)hipGetLastError();
+    b.p = nullptr;
+    if (hipMalloc(&b.p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      b.p = nullptr;
+      return fail(DTSORT_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+    }
+    want = bytes;
+  }
+  b.cap = want;
+  return 0;
+}
+
+static int get_ctx(Ctx** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_mu);
+  if ((int)g_ctx.size() <= dev) g_ctx.resize(dev + 1, nullptr);
+  if (!g_ctx[dev]) {
+    Ctx* c = new Ctx();
+    c->device = dev;
+    c->lv.resize(MAX_LEVELS);
+    if (hipHostMalloc((void**)&c->h_ctr, sizeof(LevelCounters) * MAX_LEVELS) != hipSuccess ||
+        hipHostMalloc(&c->h_stage, 1 << 16) != hipSuccess || hipEventCreateWithFlags(&c->done, hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      delete c;
+      return fail(DTSORT_ENOMEM, "pinned host allocation failed");
+    }
+    g_ctx[dev] = c;
+  }
+  *out = g_ctx[dev];
+  return 0;
+}
+
+static void free_buf(DevBuf& b) {
+  if (b.p) (void)hipFree(b.p);
+  b.p = nullptr;
+  b.cap = 0;
+}
+
+template <typename K, typename V>
+struct SortJob {
+  Bufs<K, V> bufs;
+  size_t n;
+  const uint64_t* seg;
+  uint32_t n_seg;
+  int key_bits;
+  dtsort_opts o;
+};
+
+static uint32_t cutoff_for(int kb, bool hv, int req) {
+  const uint32_t cap = (kb == 8 && hv) ? 8192u : 16384u;
+  if (req <= 0) return cap;
+  return std::min<uint32_t>(cap, std::max<uint32_t>(2u, (uint32_t)req));
+}
+
+// Tuned defaults (autotuner table); SAMPLING mode, indexed by key layout.
+struct Tuned {
+  int digit_bits;
+  int cutoff;
+};
+static Tuned tuned_params(int kb, bool hv, size_t n) {
+  (void)n;
+  (void)hv;
+  (void)kb;
+  return Tuned{8, 0};
+}
+
+template <typename K, typename V>
+static int run_sort(Ctx* c, SortJob<K, V>& J, hipStream_t s, dtsort_stats* stats);
+
+template <typename K, typename V>
+static void fill_caps(LevelArgs& a, uint32_t n_tasks, uint64_t total, int gmax, uint32_t cutoff) {
+  const uint64_t nbc = (uint64_t)nb_cap(gmax);
+  const uint64_t buckets = (uint64_t)n_tasks * nbc;
+  a.caps.tasks = (uint32_t)std::min<uint64_t>(buckets, total / (cutoff + 1ull) + 1);
+  a.caps.leaf = (uint32_t)std::min<uint64_t>(buckets, total / 2 + 1);
+  a.caps.copies = (uint32_t)std::min<uint64_t>(buckets + total / (1u << 20) + 1, total + 1);
+  a.caps.merges = (uint32_t)std::min<uint64_t>((uint64_t)n_tasks << (gmax - 1), total + 1);
+  a.caps.munits = (uint32_t)(total / 4096 + a.caps.merges + 1);
+  a.caps.spills = (uint32_t)(total / (1u << 20) + a.caps.merges + 1);
+}
+
+template <typename K, typename V>
+static int run_sort(Ctx* c, SortJob<K, V>& J, hipStream_t s, dtsort_stats* stats) {
+  constexpr bool HV = HasVal<V>::value;
+  const size_t n = J.n;
+  const dtsort_opts& o = J.o;
+  int gover = o.digit_bits;
+  int creq = o.lds_cutoff;
+  if (o.tuned) {
+    Tuned tp = tuned_params((int)sizeof(K), HV, n);
+    if (gover <= 0) gover = tp.digit_bits;
+    if (creq <= 0) creq = tp.cutoff;
+  }
+  const uint32_t cutoff = cutoff_for((int)sizeof(K), HV, creq);
+  LevelArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.seed = o.seed;
+  a.g_override = gover;
+  a.cutoff = cutoff;
+  a.leaf_max[0] = leaf_cap<K, V>(0);
+  a.leaf_max[1] = leaf_cap<K, V>(1);
+  a.leaf_max[2] = leaf_cap<K, V>(2);
+  a.plain = o.mode == DTSORT_MODE_PLAIN;
+  a.key_bits = J.key_bits;
+  if (stats) std::memset(stats, 0, sizeof(*stats));
+
+  int r;
+  if ((r = ensure(c->ctr, sizeof(LevelCounters) * MAX_LEVELS, s))) return r;
+  LevelCounters* dctr = (LevelCounters*)c->ctr.p;
+
+  uint32_t n_tasks = 0;
+  uint64_t total = 0;
+  uint32_t max_size = 0;
+  int cur = 0;
+  const uint64_t cap_total = std::max<uint64_t>(n, 2);
+
+  // ---- root
+  if (J.seg) {
+    // seeding writes level-0 tasks and leaves like a child-planning step
+    const int gmax0 = plan_gamma((uint32_t)std::min<size_t>(n, 0xFFFFFFFFu), gover);
+    fill_caps<K, V>(a, std::max<uint32_t>(J.n_seg, 1), cap_total, gmax0, cutoff);
+    a.caps.tasks = J.n_seg + 1;
+    a.caps.leaf = J.n_seg + 1;
+    a.caps.copies = J.n_seg + 1;
+    if ((r = ensure(c->tasks[cur], sizeof(Task) * (size_t)a.caps.tasks, s))) return r;
+    for (int k = 0; k < 3; ++k)
+      if ((r = ensure(c->leaf[k], sizeof(Leaf) * (size_t)a.caps.leaf, s))) return r;
+    if ((r = ensure(c->copies, sizeof(Leaf) * (size_t)a.caps.copies, s))) return r;
+    a.next = (Task*)c->tasks[cur].p;
+    for (int k = 0; k < 3; ++k) a.leaf[k] = (Leaf*)c->leaf[k].p;
+    a.copies = (Leaf*)c->copies.p;
+    a.ctr = dctr;
+    HIPCHK(hipMemsetAsync(dctr, 0, sizeof(LevelCounters), s));
+    launch_seed_segments<K, V>(a, J.seg, J.n_seg, n, s);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(c->h_ctr, dctr, sizeof(LevelCounters), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const LevelCounters h = c->h_ctr[0];
+    if (h.error & ERR_SEGMENTS) return fail(DTSORT_EINVAL, "segment offsets are not valid");
+    if (h.error) return fail(DTSORT_EINTERNAL, "capacity check failed while seeding segments");
+    for (int k = 0; k < 3; ++k) launch_leaf<K, V>((Leaf*)c->leaf[k].p, h.leaf[k], k, J.bufs, s);
+    HIPCHK(hipGetLastError());
+    if (stats) stats->leaf_sorts += h.leaf[0] + h.leaf[1] + h.leaf[2], stats->records_leaf_sorted += h.st_leaf_records;
+    n_tasks = h.next_tasks;
+    total = h.next_records;
+    max_size = h.next_max_size;
+    // the root leaves must finish before level 0 reuses the leaf lists: the
+    // next children step is enqueued after them on the same stream.
+  } else {
+    if (n <= 1) return 0;
+    if (n <= cutoff) {
+      if ((r = ensure(c->leaf[0], sizeof(Leaf), s))) return r;
+      Leaf* hl = (Leaf*)c->h_stage;
+      HIPCHK(hipStreamSynchronize(s));  // staging buffer reuse
+      hl->off = 0;
+      hl->size = (uint32_t)n;
+      hl->bits = (uint8_t)J.key_bits;
+      hl->from = 0;
+      hl->to = 0;
+      hl->pad = 0;
+      HIPCHK(hipMemcpyAsync(c->leaf[0].p, hl, sizeof(Leaf), hipMemcpyHostToDevice, s));
+      const int cls = n <= leaf_cap<K, V>(0) ? 0 : (n <= leaf_cap<K, V>(1) ? 1 : 2);
+      launch_leaf<K, V>((Leaf*)c->leaf[0].p, 1, cls, J.bufs, s);
+      HIPCHK(hipGetLastError());
+      if (stats) stats->leaf_sorts = 1, stats->records_leaf_sorted = n;
+      return 0;
+    }
+    if ((r = ensure(c->tasks[cur], sizeof(Task), s))) return r;
+    Task* ht = (Task*)c->h_stage;
+    HIPCHK(hipStreamSynchronize(s));
+    std::memset(ht, 0, sizeof(Task));
+    ht->off = 0;
+    ht->size = (uint32_t)n;
+    ht->n_root = (uint32_t)n;
+    ht->level = 0;
+    ht->hi = (uint8_t)J.key_bits;
+    ht->src = 0;
+    ht->tgt = 0;
+    ht->flags = 0;
+    ht->gamma = (uint8_t)plan_gamma((uint32_t)n, gover);
+    HIPCHK(hipMemcpyAsync(c->tasks[cur].p, ht, sizeof(Task), hipMemcpyHostToDevice, s));
+    n_tasks = 1;
+    total = n;
+    max_size = (uint32_t)n;
+  }
+
+  // ---- levels
+  int L = 0;
+  for (; n_tasks > 0; ++L) {
+    if (L >= MAX_LEVELS) return fail(DTSORT_EINTERNAL, "recursion deeper than expected");
+    const int gmax = plan_gamma(max_size, gover);
+    // chunk: a multiple of 8192 records aiming at ~2048 units per level
+    uint64_t chunk = (total + 2047) / 2048;
+    chunk = std::max<uint64_t>(8192, (chunk + 8191) / 8192 * 8192);
+    const uint64_t units = total / chunk + n_tasks + 1;
+    const SlotLayout sl = slot_layout(gmax, false);
+    const uint64_t tab_bytes = (uint64_t)n_tasks * sl.bytes;
+    const uint64_t cm_entries = units * (uint64_t)nb_cap(gmax);
+    LevelKeep& K_ = c->lv[L];
+    fill_caps<K, V>(a, n_tasks, total, gmax, cutoff);
+    a.caps.units = (uint32_t)units;
+    a.caps.cm = cm_entries;
+    a.caps.tab = tab_bytes;
+    if ((r = ensure(c->units, sizeof(uint2) * units, s))) return r;
+    if ((r = ensure(c->cm, 4 * cm_entries, s))) return r;
+    if ((r = ensure(K_.tab, tab_bytes, s))) return r;
+    if ((r = ensure(c->tasks[1 - cur], sizeof(Task) * (size_t)a.caps.tasks, s))) return r;
+    for (int k = 0; k < 3; ++k)
+      if ((r = ensure(c->leaf[k], sizeof(Leaf) * (size_t)a.caps.leaf, s))) return r;
+    if ((r = ensure(c->copies, sizeof(Leaf) * (size_t)a.caps.copies, s))) return r;
+    if ((r = ensure(K_.merges, sizeof(Merge) * (size_t)a.caps.merges, s))) return r;
+    if ((r = ensure(K_.munits, sizeof(uint2) * (size_t)a.caps.munits, s))) return r;
+    if ((r = ensure(K_.spills, sizeof(Leaf) * (size_t)a.caps.spills, s))) return r;
+    a.tasks = (Task*)c->tasks[cur].p;
+    a.n_tasks = n_tasks;
+    a.chunk = (uint32_t)chunk;
+    a.units = (uint2*)c->units.p;
+    a.tab = (uint8_t*)K_.tab.p;
+    a.slot_bytes = sl.bytes;
+    a.cm = (uint32_t*)c->cm.p;
+    a.next = (Task*)c->tasks[1 - cur].p;
+    for (int k = 0; k < 3; ++k) a.leaf[k] = (Leaf*)c->leaf[k].p;
+    a.copies = (Leaf*)c->copies.p;
+    a.merges = (Merge*)K_.merges.p;
+    a.spills = (Leaf*)K_.spills.p;
+    a.ctr = dctr + L;
+    HIPCHK(hipMemsetAsync(a.ctr, 0, sizeof(LevelCounters), s));
+    launch_prep(a, s);
+    launch_plan<K>(a, J.bufs.k[0], J.bufs.k[1], s);
+    const uint32_t max_chunks = (uint32_t)(max_size / chunk + 1);
+    launch_distribute<K, V>(a, J.bufs, gmax, max_chunks, s);
+    launch_children<K, V>(a, J.bufs, s);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(c->h_ctr + L, a.ctr, sizeof(LevelCounters), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const LevelCounters h = c->h_ctr[L];
+    if (h.error) return fail(DTSORT_EINTERNAL, "device capacity check failed (flags " + std::to_string(h.error) + ")");
+    for (int k = 0; k < 3; ++k) launch_leaf<K, V>((Leaf*)c->leaf[k].p, h.leaf[k], k, J.bufs, s);
+    launch_copy<K, V>((Leaf*)c->copies.p, h.copies, J.bufs, s);
+    K_.n_merges = h.merges;
+    K_.n_munits = h.merge_units;
+    K_.n_spills = h.spills;
+    launch_merge_units((Merge*)K_.merges.p, h.merges, (uint2*)K_.munits.p, s);
+    HIPCHK(hipGetLastError());
+    if (stats) {
+      stats->levels += 1;
+      stats->tasks += h.st_tasks;
+      stats->records_distributed += h.st_distributed;
+      stats->heavy_keys += h.st_heavy_keys;
+      stats->heavy_records += h.st_heavy_records;
+      stats->merges += h.merges;
+      stats->records_merged += h.st_merge_records;
+      stats->leaf_sorts += h.leaf[0] + h.leaf[1] + h.leaf[2];
+      stats->records_leaf_sorted += h.st_leaf_records;
+      stats->records_copied += h.st_copy_records;
+      stats->overflow_records += h.st_overflow_records;
+    }
+    n_tasks = h.next_tasks;
+    total = h.next_records;
+    max_size = h.next_max_size;
+    cur = 1 - cur;
+  }
+  // ---- dovetail merges, deepest level first
+  for (int l = L - 1; l >= 0; --l) {
+    LevelKeep& K_ = c->lv[l];
+    if (K_.n_merges == 0) continue;
+    launch_copy<K, V>((Leaf*)K_.spills.p, K_.n_spills, J.bufs, s);
+    launch_merge<K, V>((Merge*)K_.merges.p, K_.n_merges, (uint2*)K_.munits.p, K_.n_munits, (uint8_t*)K_.tab.p,
+                       J.bufs, s);
+    HIPCHK(hipGetLastError());
+  }
+  return 0;
+}
+
+template <typename K, typename V>
+static int sort_entry(K* keys, V* vals, size_t n, const uint64_t* seg, size_t n_seg, const dtsort_opts* opts,
+                      void* stream) {
+  constexpr bool HV = HasVal<V>::value;
+  g_err.clear();
+  dtsort_opts o;
+  dtsort_default_opts(&o);
+  if (opts) o = *opts;
+  if (n >= (1ull << 32)) return fail(DTSORT_EINVAL, "n must be below 2^32");
+  if (n > 0 && !keys) return fail(DTSORT_EINVAL, "keys is NULL");
+  if (HV && n > 0 && !vals) return fail(DTSORT_EINVAL, "values is NULL");
+  if (HV && n > 0) {
+    const char* a0 = (const char*)keys;
+    const char* a1 = a0 + n * sizeof(K);
+    const char* b0 = (const char*)vals;
+    const char* b1 = b0 + n * sizeof(V);
+    if (a0 < b1 && b0 < a1) return fail(DTSORT_EINVAL, "keys and values overlap");
+  }
+  const int kbits = (int)(8 * sizeof(K));
+  int key_bits = o.key_bits > 0 ? o.key_bits : kbits;
+  if (key_bits > kbits) return fail(DTSORT_EINVAL, "key_bits larger than the key width");
+  if (o.mode < 0 || o.mode > 2) return fail(DTSORT_EINVAL, "unknown mode");
+  if (o.digit_bits < 0 || o.digit_bits > 16) return fail(DTSORT_EINVAL, "digit_bits out of range");
+  if (seg && n_seg == 0) return 0;
+  if (!seg && n <= 1) return 0;
+  if (seg && n_seg >= (1ull << 31)) return fail(DTSORT_EINVAL, "too many segments");
+  hipStream_t s = (hipStream_t)stream;
+  Ctx* c;
+  int r;
+  if ((r = get_ctx(&c))) return r;
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (c->has_last && c->last_stream != s) HIPCHK(hipStreamWaitEvent(s, c->done, 0));
+  SortJob<K, V> J;
+  J.n = n;
+  J.seg = seg;
+  J.n_seg = (uint32_t)n_seg;
+  J.key_bits = key_bits;
+  J.o = o;
+  J.bufs.k[0] = keys;
+  if constexpr (HV) J.bufs.v[0] = vals;
+  // ping-pong partner
+  const size_t need = dtsort_workspace_bytes((int)sizeof(K), HV ? (int)sizeof(V) : 0, n);
+  char* ws;
+  if (o.workspace) {
+    if (o.workspace_bytes < need) return fail(DTSORT_EWORKSPACE, "workspace smaller than dtsort_workspace_bytes()");
+    ws = (char*)o.workspace;
+  } else {
+    if ((r = ensure(c->tk, need, s))) return r;
+    ws = (char*)c->tk.p;
+  }
+  J.bufs.k[1] = (K*)ws;
+  if constexpr (HV) J.bufs.v[1] = (V*)(ws + ((n * sizeof(K) + 255) & ~(size_t)255));
+  r = run_sort<K, V>(c, J, s, o.stats);
+  if (hipEventRecord(c->done, s) == hipSuccess) {
+    c->has_last = true;
+    c->last_stream = s;
+  }
+  return r;
+}
+
+}  // namespace dts
+
+using namespace dts;
+
+extern "C" {
+
+void dtsort_default_opts(dtsort_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->mode = DTSORT_MODE_SAMPLING;
+}
+
+size_t dtsort_workspace_bytes(int key_bytes, int val_bytes, size_t n) {
+  const size_t kb = ((size_t)key_bytes * n + 255) & ~(size_t)255;
+  const size_t vb = ((size_t)val_bytes * n + 255) & ~(size_t)255;
+  return kb + vb + 256;
+}
+
+int dtsort_u32(uint32_t* keys, size_t n, const dtsort_opts* opts, void* stream) {
+  return sort_entry<uint32_t, NoVal>(keys, (NoVal*)nullptr, n, nullptr, 0, opts, stream);
+}
+
+int dtsort_u64(uint64_t* keys, size_t n, const dtsort_opts* opts, void* stream) {
+  return sort_entry<uint64_t, NoVal>(keys, (NoVal*)nullptr, n, nullptr, 0, opts, stream);
+}
+
+int dtsort_pairs_u64(uint64_t* keys, uint64_t* values, size_t n, const dtsort_opts* opts, void* stream) {
+  return sort_entry<uint64_t, uint64_t>(keys, values, n, nullptr, 0, opts, stream);
+}
+
+int dtsort_segmented(uint32_t* keys, uint32_t* values, size_t n_total, const uint64_t* seg_offsets, size_t n_segments,
+                     const dtsort_opts* opts, void* stream) {
+  if (!seg_offsets && n_segments > 0) return fail(DTSORT_EINVAL, "seg_offsets is NULL");
+  if (values) return sort_entry<uint32_t, uint32_t>(keys, values, n_total, seg_offsets, n_segments, opts, stream);
+  return sort_entry<uint32_t, NoVal>(keys, (NoVal*)nullptr, n_total, seg_offsets, n_segments, opts, stream);
+}
+
+void dtsort_release(void) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  for (Ctx* c : g_ctx) {
+    if (!c) continue;
+    (void)hipDeviceSynchronize();
+    free_buf(c->tk);
+    free_buf(c->tv);
+    for (auto& b : c->tasks) free_buf(b);
+    free_buf(c->units);
+    free_buf(c->cm);
+    for (auto& b : c->leaf) free_buf(b);
+    free_buf(c->copies);
+    free_buf(c->ctr);
+    free_buf(c->scratch);
+    for (auto& l : c->lv) {
+      free_buf(l.tab);
+      free_buf(l.merges);
+      free_buf(l.munits);
+      free_buf(l.spills);
+    }
+    if (c->h_ctr) (void)hipHostFree(c->h_ctr);
+    if (c->h_stage) (void)hipHostFree(c->h_stage);
+    if (c->done) (void)hipEventDestroy(c->done);
+    delete c;
+  }
+  g_ctx.clear();
+}
+
+const char* dtsort_last_error(void) { return g_err.c_str(); }
+
+const char* dtsort_strerror(int st) {
+  switch (st) {
+    case DTSORT_OK: return "ok";
+    case DTSORT_EINVAL: return "invalid argument";
+    case DTSORT_ENOMEM: return "out of device memory";
+    case DTSORT_EWORKSPACE: return "workspace too small";
+    case DTSORT_EHIP: return "HIP runtime error";
+    case DTSORT_EINTERNAL: return "internal capacity or consistency check failed";
+    default: return "unknown status";
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,355 @@
+// Learned partitioner (not part of the paper): an FP32 CDF model
+// 1 -> 64 -> 64 -> 1 (ReLU hidden layers) trained on the method's own sorted
+// sample, used to propose the root level's zone splitters.  All arithmetic
+// runs on the FP32 vector units.
+//
+// Parameter layout (4353 floats): W1[64], b1[64], W2[64][64] (row = output
+// unit), b2[64], W3[64], b3.  Loss: mean squared error.  Optimiser: Adam.
+// Inputs: x = log-linear transform of the key (one unit per binary order of
+// magnitude, linear inside it), rescaled to [0, 1] over the sample; target
+// y = (rank + 0.5) / N.  Batches: step s uses samples j*stride + (s mod
+// stride), j < batch, stride = N / batch.
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "block_sort.hpp"
+#include "launch.hpp"
+
+namespace dts {
+
+constexpr int NP = 4353;
+constexpr int OW1 = 0, OB1 = 64, OW2 = 128, OB2 = 128 + 4096, OW3 = 128 + 4096 + 64, OB3 = 128 + 4096 + 128;
+constexpr int GT = 128;  // samples (threads) per gradient workgroup
+
+__device__ inline double u01(uint64_t h, uint64_t i) {
+  return (double)(mix64(h + (i + 1) * GOLD) >> 11) * (1.0 / 9007199254740992.0);
+}
+
+// Deterministic initialisation: per hidden unit of layer 1 a kink in [0, 1),
+// slope magnitude sqrt(6) (0.5 + 0.5 u), random sign; W2, W3 uniform in
+// +-sqrt(6/64); b2 = 0, b3 = 0.5.  Computed in double, stored as float.
+__global__ void k_mlp_init(float* p, uint64_t seed) {
+  const uint64_t h = mix64(mix64(seed + GOLD) ^ 0x4D4C50ull);
+  const double s6 = 2.449489742783178;       // sqrt(6)
+  const double s664 = 0.30618621784789724;   // sqrt(6/64)
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < NP; i += gridDim.x * blockDim.x) {
+    float v = 0.0f;
+    if (i < OB1) {
+      const double a = u01(h, 3ull * i);
+      const double mag = s6 * (0.5 + 0.5 * u01(h, 3ull * i + 1));
+      const double sg = u01(h, 3ull * i + 2) < 0.5 ? -1.0 : 1.0;
+      v = (float)(sg * mag);
+    } else if (i < OW2) {
+      const int j = i - OB1;
+      const int iw = OW1 + j;
+      const double a = u01(h, 3ull * iw);
+      const double mag = s6 * (0.5 + 0.5 * u01(h, 3ull * iw + 1));
+      const double sg = u01(h, 3ull * iw + 2) < 0.5 ? -1.0 : 1.0;
+      v = (float)(-(sg * mag) * a);
+    } else if (i < OB2) {
+      v = (float)((2.0 * u01(h, 3ull * i) - 1.0) * s664);
+    } else if (i < OW3) {
+      v = 0.0f;
+    } else if (i < OB3) {
+      v = (float)((2.0 * u01(h, 3ull * i) - 1.0) * s664);
+    } else {
+      v = 0.5f;
+    }
+    p[i] = v;
+  }
+}
+
+template <typename K>
+__device__ inline double loglinear(K k, int kb) {
+  if (k == 0) return 0.0;
+  const int e = bit_length(k) - 1;
+  const K p = (K)1 << e;
+  const double frac = (double)(k - p) / (double)p;
+  return ((double)e + 1.0 + frac) / (double)(kb + 1);
+}
+
+// x, y from the sorted sample keys.
+template <typename K>
+__global__ void k_mlp_data(const K* sk, uint32_t n, int kb, float* x, float* y) {
+  const double t0 = loglinear<K>(sk[0], kb);
+  const double span = loglinear<K>(sk[n - 1], kb) - t0;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const double t = loglinear<K>(sk[i], kb);
+    x[i] = span > 0 ? (float)((t - t0) / span) : 0.0f;
+    y[i] = (float)(((double)i + 0.5) / (double)n);
+  }
+}
+
+// Forward + backward for GT samples per workgroup; writes this workgroup's
+// partial gradient (and partial loss at index NP) to part[blockIdx.x].
+// Samples: j = blockIdx.x * GT + t < batch; data index j*stride + off
+// (stride 0 = contiguous).  The mean is over `batch`.
+__global__ __launch_bounds__(GT) void k_mlp_grad(const float* __restrict__ p, const float* __restrict__ x,
+                                                 const float* __restrict__ y, uint32_t batch, uint32_t stride,
+                                                 uint32_t off, float* __restrict__ part) {
+  __shared__ float P[NP];
+  __shared__ float A[GT][65];  // h1, later dz1 * x
+  __shared__ float B[GT][65];  // dz2, later d * h2
+  __shared__ float red[GT / WAVE];
+  const int t = threadIdx.x;
+  for (int i = t; i < NP; i += GT) P[i] = p[i];
+  __syncthreads();
+  const uint32_t j = blockIdx.x * GT + t;
+  const bool valid = j < batch;
+  const uint32_t di = stride ? j * stride + off : j;
+  const float xs = valid ? x[di] : 0.0f;
+  const float ys = valid ? y[di] : 0.0f;
+  float h1[64], z2[64];
+#pragma unroll
+  for (int i = 0; i < 64; ++i) h1[i] = fmaxf(fmaf(P[OW1 + i], xs, P[OB1 + i]), 0.0f);
+#pragma unroll 4
+  for (int o = 0; o < 64; ++o) {
+    float s = P[OB2 + o];
+#pragma unroll
+    for (int i = 0; i < 64; ++i) s = fmaf(P[OW2 + o * 64 + i], h1[i], s);
+    z2[o] = s;
+  }
+  float yh = P[OB3];
+#pragma unroll
+  for (int o = 0; o < 64; ++o) yh = fmaf(P[OW3 + o], fmaxf(z2[o], 0.0f), yh);
+  const float err = valid ? (yh - ys) : 0.0f;
+  const float d = 2.0f * err / (float)batch;
+  // dz2 (kept in z2's registers after h2 has been used) and B = dz2
+#pragma unroll
+  for (int o = 0; o < 64; ++o) {
+    const float dz = z2[o] > 0.0f ? d * P[OW3 + o] : 0.0f;
+    A[t][o] = h1[o];
+    B[t][o] = dz;
+  }
+  // dh1 = W2^T dz2 -> dz1
+  float dz1[64];
+#pragma unroll
+  for (int i = 0; i < 64; ++i) dz1[i] = 0.0f;
+#pragma unroll 4
+  for (int o = 0; o < 64; ++o) {
+    const float dz = B[t][o];
+#pragma unroll
+    for (int i = 0; i < 64; ++i) dz1[i] = fmaf(P[OW2 + o * 64 + i], dz, dz1[i]);
+  }
+  __syncthreads();
+  float* out = part + (size_t)blockIdx.x * (NP + 1);
+  // dW2[o][i] = sum_s B[s][o] A[s][i]; db2[o] = sum_s B[s][o]
+  for (int e = t; e < 4096; e += GT) {
+    const int o = e >> 6, i = e & 63;
+    float s = 0.0f;
+    for (int r = 0; r < GT; ++r) s = fmaf(B[r][o], A[r][i], s);
+    out[OW2 + e] = s;
+  }
+  if (t < 64) {
+    float s = 0.0f;
+    for (int r = 0; r < GT; ++r) s += B[r][t];
+    out[OB2 + t] = s;
+  }
+  __syncthreads();
+  // second pass: A = dz1 (masked), B = d * h2
+#pragma unroll
+  for (int i = 0; i < 64; ++i) {
+    A[t][i] = h1[i] > 0.0f ? dz1[i] : 0.0f;
+    B[t][i] = d * fmaxf(z2[i], 0.0f);
+  }
+  __syncthreads();
+  if (t < 64) {
+    float sb = 0.0f, s3 = 0.0f;
+    for (int r = 0; r < GT; ++r) {
+      sb += A[r][t];
+      s3 += B[r][t];
+    }
+    out[OB1 + t] = sb;
+    out[OW3 + t] = s3;
+  }
+  // dW1[i] = sum_s dz1[s][i] * x_s: scale A rows by x_s, then column sums
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 64; ++i) A[t][i] *= xs;
+  __syncthreads();
+  if (t < 64) {
+    float s = 0.0f;
+    for (int r = 0; r < GT; ++r) s += A[r][t];
+    out[OW1 + t] = s;
+  }
+  // db3 = sum d ; loss = sum err^2 / batch
+  float db3 = d, ls = err * err / (float)batch;
+#pragma unroll
+  for (int o = WAVE / 2; o > 0; o >>= 1) {
+    db3 += __shfl_xor(db3, o, WAVE);
+    ls += __shfl_xor(ls, o, WAVE);
+  }
+  __shared__ float red2[GT / WAVE];
+  if ((t & (WAVE - 1)) == 0) {
+    red[t / WAVE] = db3;
+    red2[t / WAVE] = ls;
+  }
+  __syncthreads();
+  if (t == 0) {
+    float a = 0.0f, b = 0.0f;
+    for (int w = 0; w < GT / WAVE; ++w) {
+      a += red[w];
+      b += red2[w];
+    }
+    out[OB3] = a;
+    out[NP] = b;
+  }
+}
+
+// Sum the partial gradients in workgroup order (deterministic).  adam = 0:
+// write the gradient and loss; adam = 1: Adam update of p, m, v at step
+// `step` (1-based) and record the loss.
+__global__ void k_mlp_reduce(const float* __restrict__ part, uint32_t nwg, float* p, float* m, float* v,
+                             float* grad, float* loss_out, int adam, int step, float lr) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i > NP) return;
+  float g = 0.0f;
+  for (uint32_t w = 0; w < nwg; ++w) g += part[(size_t)w * (NP + 1) + i];
+  if (i == NP) {
+    if (loss_out) *loss_out = g;
+    return;
+  }
+  if (!adam) {
+    grad[i] = g;
+    return;
+  }
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  const float mi = b1 * m[i] + (1.0f - b1) * g;
+  const float vi = b2 * v[i] + (1.0f - b2) * g * g;
+  m[i] = mi;
+  v[i] = vi;
+  const float c1 = 1.0f - powf(b1, (float)step);
+  const float c2 = 1.0f - powf(b2, (float)step);
+  p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+__global__ __launch_bounds__(256) void k_mlp_forward(const float* __restrict__ p, const float* __restrict__ x,
+                                                     uint32_t n, float* __restrict__ pred) {
+  __shared__ float P[NP];
+  for (int i = threadIdx.x; i < NP; i += 256) P[i] = p[i];
+  __syncthreads();
+  const uint32_t j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= n) return;
+  const float xs = x[j];
+  float h1[64];
+#pragma unroll
+  for (int i = 0; i < 64; ++i) h1[i] = fmaxf(fmaf(P[OW1 + i], xs, P[OB1 + i]), 0.0f);
+  float yh = P[OB3];
+#pragma unroll 4
+  for (int o = 0; o < 64; ++o) {
+    float s = P[OB2 + o];
+#pragma unroll
+    for (int i = 0; i < 64; ++i) s = fmaf(P[OW2 + o * 64 + i], h1[i], s);
+    yh = fmaf(P[OW3 + o], fmaxf(s, 0.0f), yh);
+  }
+  pred[j] = yh;
+}
+
+// ------------------------------------------------------------ launchers
+struct MlpBufs {
+  float* p;
+  float* m;
+  float* v;
+  float* part;
+  uint32_t part_wg;  // capacity in workgroups
+};
+
+int mlp_loss_grad(const float* p, const float* x, const float* y, uint32_t n, float* grad, float* loss, float* part,
+                  hipStream_t s) {
+  const uint32_t nwg = (n + GT - 1) / GT;
+  hipLaunchKernelGGL(k_mlp_grad, dim3(nwg), dim3(GT), 0, s, p, x, y, n, 0u, 0u, part);
+  hipLaunchKernelGGL(k_mlp_reduce, dim3((NP + 1 + 255) / 256), dim3(256), 0, s, part, nwg, (float*)nullptr,
+                     (float*)nullptr, (float*)nullptr, grad, loss, 0, 0, 0.0f);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+void mlp_forward(const float* p, const float* x, uint32_t n, float* pred, hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_mlp_forward, dim3((n + 255) / 256), dim3(256), 0, s, p, x, n, pred);
+}
+
+// Full training loop: init, then `steps` Adam steps on strided batches.
+void mlp_train(const float* x, const float* y, uint32_t n, uint64_t seed, int steps, uint32_t batch, float lr,
+               float* p, float* m, float* v, float* part, float* losses, hipStream_t s) {
+  hipLaunchKernelGGL(k_mlp_init, dim3(18), dim3(256), 0, s, p, seed);
+  (void)hipMemsetAsync(m, 0, sizeof(float) * NP, s);
+  (void)hipMemsetAsync(v, 0, sizeof(float) * NP, s);
+  const uint32_t stride = n / batch;
+  const uint32_t nwg = (batch + GT - 1) / GT;
+  for (int st = 0; st < steps; ++st) {
+    hipLaunchKernelGGL(k_mlp_grad, dim3(nwg), dim3(GT), 0, s, (const float*)p, x, y, batch, stride,
+                       (uint32_t)(st % stride), part);
+    hipLaunchKernelGGL(k_mlp_reduce, dim3((NP + 1 + 255) / 256), dim3(256), 0, s, (const float*)part, nwg, p, m, v,
+                       (float*)nullptr, losses ? losses + st : (float*)nullptr, 1, st + 1, lr);
+  }
+}
+
+template <typename K>
+void mlp_data(const K* sk, uint32_t n, int kb, float* x, float* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_mlp_data<K>, dim3((n + 255) / 256), dim3(256), 0, s, sk, n, kb, x, y);
+}
+template void mlp_data<uint64_t>(const uint64_t*, uint32_t, int, float*, float*, hipStream_t);
+template void mlp_data<uint32_t>(const uint32_t*, uint32_t, int, float*, float*, hipStream_t);
+
+}  // namespace dts
+
+// ------------------------------------------------------------------ C ABI
+#include "../../include/dtsort.h"
+
+namespace {
+struct TmpF {
+  std::vector<void*> ptrs;
+  ~TmpF() {
+    for (void* q : ptrs) (void)hipFree(q);
+  }
+  float* get(size_t n) {
+    void* q = nullptr;
+    if (hipMalloc(&q, sizeof(float) * (n ? n : 1)) != hipSuccess) return nullptr;
+    ptrs.push_back(q);
+    return (float*)q;
+  }
+};
+}  // namespace
+
+extern "C" {
+
+int dtsort_mlp_loss_grad(const float* params, const float* x, const float* y, size_t n, float* grad, float* loss,
+                         void* stream) {
+  if (!params || !x || !y || !grad || !loss || n == 0 || n >= (1u << 31)) return DTSORT_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  TmpF tmp;
+  const size_t nwg = (n + dts::GT - 1) / dts::GT;
+  float* part = tmp.get(nwg * (dts::NP + 1));
+  if (!part) return DTSORT_ENOMEM;
+  if (dts::mlp_loss_grad(params, x, y, (uint32_t)n, grad, loss, part, s)) return DTSORT_EHIP;
+  return hipStreamSynchronize(s) == hipSuccess ? DTSORT_OK : DTSORT_EHIP;
+}
+
+int dtsort_mlp_forward(const float* params, const float* x, size_t n, float* pred, void* stream) {
+  if (!params || !x || !pred || n >= (1u << 31)) return DTSORT_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  dts::mlp_forward(params, x, (uint32_t)n, pred, s);
+  if (hipGetLastError() != hipSuccess) return DTSORT_EHIP;
+  return hipStreamSynchronize(s) == hipSuccess ? DTSORT_OK : DTSORT_EHIP;
+}
+
+int dtsort_mlp_train_u64(const uint64_t* sorted_keys, size_t n, uint64_t seed, int steps, int batch, float lr,
+                         float* params, float* losses, void* stream) {
+  if (!sorted_keys || !params || n < 2 || n >= (1u << 31) || steps < 0 || batch <= 0 || (size_t)batch > n || !(lr > 0))
+    return DTSORT_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  TmpF tmp;
+  float* x = tmp.get(n);
+  float* y = tmp.get(n);
+  float* m = tmp.get(dts::NP);
+  float* v = tmp.get(dts::NP);
+  float* part = tmp.get(((size_t)batch + dts::GT - 1) / dts::GT * (dts::NP + 1));
+  if (!x || !y || !m || !v || !part) return DTSORT_ENOMEM;
+  dts::mlp_data<uint64_t>(sorted_keys, (uint32_t)n, 64, x, y, s);
+  dts::mlp_train(x, y, (uint32_t)n, seed, steps, (uint32_t)batch, lr, params, m, v, part, losses, s);
+  if (hipGetLastError() != hipSuccess) return DTSORT_EHIP;
+  return hipStreamSynchronize(s) == hipSuccess ? DTSORT_OK : DTSORT_EHIP;
+}
+
+}  // extern "C"

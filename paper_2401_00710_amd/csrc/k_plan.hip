@@ -1,0 +1,214 @@
+// Step 1 of Alg. 2 (Section 3.1; the sampled key range and overflow bucket of
+// Section 5), one workgroup per subproblem, and the base case of Section 3.5
+// (a stable sort in LDS), one workgroup per small subproblem.
+#include "block_sort.hpp"
+#include "launch.hpp"
+
+namespace dts {
+
+// ------------------------------------------------------------------- plan
+// Draws 2^g * t sample keys at counter-based random positions (with
+// replacement), sorts them in LDS, takes the key range from the sample
+// maximum, marks keys that fill two or more of the 2^g subsample slots
+// S[0], S[t], S[2t], ... as heavy, and writes the light-id table L (per zone:
+// its light id = zone + number of heavy keys in lower zones; the last entry is
+// the overflow id) and the heavy keys (ascending) into the task's table slot.
+template <typename K>
+__global__ __launch_bounds__(1024) void k_plan(LevelArgs a, const K* k0, const K* k1) {
+  constexpr int T = 1024;
+  constexpr int ITEMS = sizeof(K) == 4 ? 32 : 16;
+  constexpr int CAP = T * ITEMS;  // sample capacity
+  __shared__ K sk[CAP];
+  __shared__ uint32_t cnt[bsort_cnt_words<T>()];
+  __shared__ K red[2 * (T / WAVE)];
+  __shared__ uint32_t hz[1 << (GMAX - 1)];
+  __shared__ uint32_t tmp[T / WAVE + 1];
+  __shared__ int s_top, s_w, s_shift;
+
+  Task& tr = a.tasks[blockIdx.x];
+  const Task t = tr;
+  if (t.flags & TF_LEARNED) return;  // planned by the learned-partitioner step
+  const int g = t.gamma;
+  const int hi = t.hi;
+  const SlotLayout sl = slot_layout(g, false);
+  uint8_t* slot = a.tab + t.tab_off;
+  uint32_t* gL = (uint32_t*)(slot + sl.light);
+  uint64_t* gH = (uint64_t*)(slot + sl.heavy);
+  uint32_t nh = 0;
+
+  if (hi <= g) {
+    // last digit: every remaining bit in one plain digit; no sample needed
+    if (threadIdx.x == 0) {
+      s_top = hi;
+      s_w = hi;
+      s_shift = 0;
+    }
+  } else {
+    const uint32_t lgn = 32 - __builtin_clz(max(t.n_root - 1u, 1u));
+    uint32_t ts = min(lgn, (uint32_t)(CAP >> g));
+    ts = max(ts, 1u);
+    const uint32_t ns = ts << g;
+    const uint64_t sb = sample_base(a.seed, t.off, t.level);
+    const K* keys = (t.src ? k1 : k0) + t.off;
+    K kk[ITEMS];
+    uint16_t dummy[ITEMS];
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+      const uint32_t e = (uint32_t)striped_index<T, ITEMS>(i);
+      if (e < ns) {
+        const uint64_t r = mix64(sb + (uint64_t)(e + 1) * GOLD);
+        const uint64_t p = __umul64hi(r, (uint64_t)t.size);
+        kk[i] = keys[p];
+      } else {
+        kk[i] = ~(K)0;
+      }
+    }
+    K vor, vand;
+    block_or_and<K, T, ITEMS>(kk, (int)ns, red, &vor, &vand);
+    const K diff = (vor ^ vand) & mask_below<K>(hi);
+    if (diff) {
+      block_radix_sort<K, T, ITEMS, false>(kk, dummy, trailing_zeros(diff), bit_length(diff), sk, nullptr, cnt);
+    } else {
+#pragma unroll
+      for (int i = 0; i < ITEMS; ++i) sk[striped_index<T, ITEMS>(i)] = kk[i];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      const K mx = sk[ns - 1] & mask_below<K>(hi);
+      const int top = (t.flags & TF_SKIP_DISABLED) ? hi : bit_length(mx);
+      const int w = min(g, top);
+      s_top = top;
+      s_w = w;
+      s_shift = top - w;
+    }
+    __syncthreads();
+    if (!a.plain) {
+      // heavy: the first slot of every run of >= 2 equal subsample slots
+      const uint32_t nsub = 1u << g;
+      const uint32_t j = threadIdx.x;  // nsub <= 1024
+      bool f = false;
+      K kj = 0;
+      if (j + 1 < nsub) {
+        kj = sk[j * ts];
+        f = (kj == sk[(j + 1) * ts]) && (j == 0 || sk[(j - 1) * ts] != kj);
+      }
+      uint32_t total;
+      const uint32_t idx = block_excl_scan<T>(f ? 1u : 0u, tmp, &total);
+      nh = total;
+      if (f) {
+        gH[idx] = (uint64_t)kj;
+        const K low = kj & mask_below<K>(hi);
+        hz[idx] = (uint32_t)(shr<K>(low, s_shift) & (K)((1u << s_w) - 1u));
+      }
+      __syncthreads();
+    }
+  }
+  __syncthreads();
+  const int w = s_w;
+  // light ids: L[z] = z + #{heavy keys with zone < z}; zones of the sorted heavy keys are non-decreasing
+  const uint32_t zones = 1u << w;
+  for (uint32_t z = threadIdx.x; z <= zones; z += T) {
+    uint32_t lo = 0, n = nh;
+    while (n > 0) {
+      const uint32_t half = n >> 1;
+      if (hz[lo + half] < z) {
+        lo += half + 1;
+        n -= half + 1;
+      } else {
+        n = half;
+      }
+    }
+    gL[z] = z + lo;
+  }
+  if (threadIdx.x == 0) {
+    tr.w = (uint8_t)w;
+    tr.shift = (uint8_t)s_shift;
+    tr.top = (uint8_t)s_top;
+    tr.n_heavy = (uint16_t)nh;
+    tr.n_buckets = (uint16_t)(zones + nh + 1);
+  }
+}
+
+template <typename K>
+void launch_plan(const LevelArgs& a, const K* k0, const K* k1, hipStream_t s) {
+  hipLaunchKernelGGL(k_plan<K>, dim3(a.n_tasks), dim3(1024), 0, s, a, k0, k1);
+}
+
+// ---------------------------------------------------------------- leaves
+// Base case: a stable radix sort in LDS of a subproblem of at most T*ITEMS
+// records, only over the bit range in which its keys differ.
+template <typename K, typename V, int T, int ITEMS>
+__global__ __launch_bounds__(T) void k_leaf(const Leaf* items, Bufs<K, V> bf) {
+  constexpr int N = T * ITEMS;
+  constexpr bool HV = HasVal<V>::value;
+  __shared__ K sk[N];
+  __shared__ uint16_t si[HV ? N : 1];
+  __shared__ uint32_t cnt[bsort_cnt_words<T>()];
+  __shared__ K red[2 * (T / WAVE)];
+  const Leaf it = items[blockIdx.x];
+  const K* kin = bf.k[it.from] + it.off;
+  K* kout = bf.k[it.to] + it.off;
+  const int n = (int)it.size;
+  K kk[ITEMS];
+  uint16_t ix[ITEMS];
+#pragma unroll
+  for (int i = 0; i < ITEMS; ++i) {
+    const int e = striped_index<T, ITEMS>(i);
+    kk[i] = e < n ? kin[e] : ~(K)0;
+    ix[i] = (uint16_t)e;
+  }
+  K vor, vand;
+  block_or_and<K, T, ITEMS>(kk, n, red, &vor, &vand);
+  const K diff = (vor ^ vand) & mask_below<K>(it.bits);
+  if (diff) {
+    block_radix_sort<K, T, ITEMS, HV>(kk, ix, trailing_zeros(diff), bit_length(diff), sk, si, cnt);
+  }
+#pragma unroll
+  for (int i = 0; i < ITEMS; ++i) {
+    const int e = striped_index<T, ITEMS>(i);
+    if (e < n) kout[e] = kk[i];
+  }
+  if constexpr (HV) {
+    const V* vin = bf.v[it.from] + it.off;
+    V* vout = bf.v[it.to] + it.off;
+    // gather all values first: `to` may equal `from`
+    V vv[ITEMS];
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+      const int e = striped_index<T, ITEMS>(i);
+      if (e < n) vv[i] = vin[ix[i]];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+      const int e = striped_index<T, ITEMS>(i);
+      if (e < n) vout[e] = vv[i];
+    }
+  }
+}
+
+template <typename K, typename V>
+void launch_leaf(const Leaf* items, uint32_t n_items, int cls, Bufs<K, V> b, hipStream_t s) {
+  if (n_items == 0) return;
+  constexpr bool big8 = sizeof(K) == 8 && HasVal<V>::value;
+  if (cls == 0) {
+    hipLaunchKernelGGL((k_leaf<K, V, 256, 8>), dim3(n_items), dim3(256), 0, s, items, b);
+  } else if constexpr (big8) {
+    hipLaunchKernelGGL((k_leaf<K, V, 512, 16>), dim3(n_items), dim3(512), 0, s, items, b);
+  } else if (cls == 1) {
+    hipLaunchKernelGGL((k_leaf<K, V, 512, 16>), dim3(n_items), dim3(512), 0, s, items, b);
+  } else {
+    hipLaunchKernelGGL((k_leaf<K, V, 1024, 16>), dim3(n_items), dim3(1024), 0, s, items, b);
+  }
+}
+
+template void launch_plan<uint32_t>(const LevelArgs&, const uint32_t*, const uint32_t*, hipStream_t);
+template void launch_plan<uint64_t>(const LevelArgs&, const uint64_t*, const uint64_t*, hipStream_t);
+#define DTS_INST(K, V) template void launch_leaf<K, V>(const Leaf*, uint32_t, int, Bufs<K, V>, hipStream_t);
+DTS_INST(uint32_t, NoVal)
+DTS_INST(uint64_t, NoVal)
+DTS_INST(uint64_t, uint64_t)
+DTS_INST(uint32_t, uint32_t)
+#undef DTS_INST
+
+}  // namespace dts

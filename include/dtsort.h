@@ -79,19 +79,28 @@ typedef struct dtsort_stats {
   float learned_balance;        /* LEARNED mode: balance error of the model's zones */
   float sampling_balance;       /* LEARNED mode: balance error of the digit zones */
   float learned_final_loss;     /* LEARNED mode: training loss of the last step */
-  double learned_ms;            /* LEARNED mode: time spent training + judging (ms) */
+  double learned_ms;            /* LEARNED mode: time spent sampling, training and judging (ms) */
+  /* Filled only when opts->profile is set: per kernel kind (0 plan, 1 histogram,
+   * 2 scans, 3 scatter, 4 child planning, 5 leaf sorts, 6 copies, 7 dovetail
+   * merges) the summed launch time measured with HIP events on `stream`, the
+   * algorithmic bytes those launches move (records x record bytes, read +
+   * write; histogram: read only), and the number of launches. */
+  double kernel_ms[8];
+  double kernel_bytes[8];
+  uint32_t kernel_launches[8];
 } dtsort_stats;
 
 typedef struct dtsort_opts {
   uint64_t seed;          /* seed of the sampling generator (Appendix A: deterministic given it) */
   int32_t key_bits;       /* 0 = full width; else keys are < 2^key_bits (the paper's optional bit count) */
   int32_t mode;           /* dtsort_mode */
-  int32_t digit_bits;     /* 0 = automatic (log2 of the cube root of n', clamped to [8, 11]); else 1..11 */
+  int32_t digit_bits;     /* 0 = automatic (log2 of the cube root of n', clamped to [8, 10]); else 1..10 */
   int32_t lds_cutoff;     /* 0 = automatic; base-case threshold theta (records) */
   int32_t tuned;          /* 1 = take digit_bits / lds_cutoff from the autotuner's table when they are 0 */
   int32_t learned_steps;  /* LEARNED: optimiser steps (0 = default 512) */
   int32_t learned_batch;  /* LEARNED: batch size (0 = default 1024) */
   float learned_lr;       /* LEARNED: Adam step size (0 = default 3e-3) */
+  int32_t profile;        /* 1 = time every kernel launch with HIP events into stats (adds syncs) */
   void* workspace;        /* optional device buffer for the ping-pong partner (see dtsort_workspace_bytes) */
   size_t workspace_bytes;
   dtsort_stats* stats;    /* optional host pointer */

@@ -33,10 +33,19 @@ class Stats(C.Structure):
         ("sampling_balance", C.c_float),
         ("learned_final_loss", C.c_float),
         ("learned_ms", C.c_double),
+        ("kernel_ms", C.c_double * 8),
+        ("kernel_bytes", C.c_double * 8),
+        ("kernel_launches", C.c_uint32 * 8),
     ]
 
+    KINDS = ("plan", "hist", "scan", "scatter", "children", "leaf", "copy", "merge")
+
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        d = {}
+        for k, _ in self._fields_:
+            v = getattr(self, k)
+            d[k] = list(v) if k.startswith("kernel_") else v
+        return d
 
 
 class Opts(C.Structure):
@@ -50,6 +59,7 @@ class Opts(C.Structure):
         ("learned_steps", C.c_int32),
         ("learned_batch", C.c_int32),
         ("learned_lr", C.c_float),
+        ("profile", C.c_int32),
         ("workspace", C.c_void_p),
         ("workspace_bytes", C.c_size_t),
         ("stats", C.POINTER(Stats)),

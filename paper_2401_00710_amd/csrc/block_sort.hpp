@@ -26,18 +26,25 @@ template <int THREADS>
 constexpr int bsort_cnt_words() {
   return (THREADS / WAVE) * 256 + THREADS / WAVE + 1;
 }
+// LDS u64 words needed for the match tables of block_radix_sort with RANK_LDS.
+template <int THREADS>
+constexpr int bsort_match_words() {
+  return (THREADS / WAVE) * 256;
+}
 
 // Sorts k[] (and carries ix[] when IDX) by key bits [lo_bit, hi_bit).
 // sk: LDS array of THREADS*ITEMS keys; si: LDS array of THREADS*ITEMS u16
 // (only when IDX); cnt: bsort_cnt_words<THREADS>() u32.  On return k[]/ix[]
 // hold the sorted sequence in the striped layout and sk (si) holds it in order.
-template <typename K, int THREADS, int ITEMS, bool IDX>
+// RANK_LDS needs `mk` (bsort_match_words<THREADS>() zeroed u64 in LDS).
+template <typename K, int THREADS, int ITEMS, bool IDX, int RANK = RANK_BALLOT>
 __device__ void block_radix_sort(K (&k)[ITEMS], uint16_t (&ix)[ITEMS], int lo_bit, int hi_bit, K* sk,
-                                 uint16_t* si, uint32_t* cnt) {
+                                 uint16_t* si, uint32_t* cnt, unsigned long long* mk = nullptr) {
   constexpr int WAVES = THREADS / WAVE;
   static_assert(THREADS >= 256, "one thread per digit in the scan");
   const int wv = threadIdx.x / WAVE;
   uint32_t* tmp = cnt + WAVES * 256;
+  unsigned long long* wm = mk + (RANK == RANK_LDS ? wv * 256 : 0);
   for (int bit = lo_bit; bit < hi_bit; bit += 8) {
     const int nbits = min(8, hi_bit - bit);
     const uint32_t dmask = (1u << nbits) - 1u;
@@ -48,7 +55,12 @@ __device__ void block_radix_sort(K (&k)[ITEMS], uint16_t (&ix)[ITEMS], int lo_bi
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
       const uint32_t d = (uint32_t)(shr<K>(k[i], bit)) & dmask;
-      const uint64_t peers = match_peers(d, nbits, true);
+      uint64_t peers;
+      if constexpr (RANK == RANK_LDS) {
+        peers = lds_match(wm, d, true);
+      } else {
+        peers = match_peers(d, nbits, true);
+      }
       const uint32_t r = mbcnt(peers);
       const uint32_t c = (uint32_t)__popcll(peers);
       const uint32_t base = wc[d];

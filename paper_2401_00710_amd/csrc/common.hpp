@@ -212,6 +212,24 @@ __device__ inline uint64_t match_peers(uint32_t v, int nbits, bool valid) {
   return peers;
 }
 
+// The same peer mask through LDS: every lane ORs its lane bit into its
+// value's slot of this wave's mask table, reads the slot back, then clears
+// it (3 LDS operations instead of one ballot per bit).  LDS instructions of
+// one wave execute in issue order, so the read sees every lane's OR and the
+// clear follows every lane's read.  The table must start (and is left) zero.
+__device__ inline uint64_t lds_match(unsigned long long* wm, uint32_t v, bool valid) {
+  const unsigned long long bit = 1ull << (threadIdx.x & (WAVE - 1));
+  unsigned long long peers = 0;
+  if (valid) {
+    __hip_atomic_fetch_or(wm + v, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    peers = __hip_atomic_load(wm + v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __hip_atomic_store(wm + v, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+  return peers;
+}
+
+enum RankMode { RANK_BALLOT = 0, RANK_LDS = 1 };
+
 // Exclusive scan of one value per thread across the workgroup.  `tmp` holds
 // THREADS/64 + 1 words of LDS.  Returns the exclusive prefix; *total gets the sum.
 template <int THREADS>
@@ -270,6 +288,7 @@ struct PlanRegs {
   uint32_t nb;
   bool learned;
   bool top_full;  // top >= key width (no overflow test)
+  bool heavy;     // the task has heavy keys (else the light id of zone z is z)
 };
 
 template <typename K>
@@ -282,6 +301,7 @@ __device__ inline PlanRegs<K> plan_regs(const Task& t) {
   p.nb = t.n_buckets;
   p.learned = (t.flags & TF_LEARNED) != 0;
   p.top_full = t.top >= t.hi;
+  p.heavy = t.n_heavy != 0;
   return p;
 }
 
@@ -310,6 +330,7 @@ __device__ inline uint32_t bucket_of(K key, const PlanRegs<K>& p, const uint32_t
     if (!p.top_full && shr<K>(low, p.top) != 0) return p.nb - 1u;
     z = (uint32_t)(shr<K>(low, p.shift) & (K)((1u << p.w) - 1u));
   }
+  if (!p.heavy) return z;
   uint32_t lid = L[z];
   uint32_t m = L[z + 1] - lid - 1u;
   if (m) {

@@ -43,19 +43,77 @@ constexpr int MAX_LEVELS = 160;
 struct LevelKeep {
   DevBuf tab, merges, munits, spills;
   uint32_t n_merges = 0, n_munits = 0, n_spills = 0;
+  double merge_records = 0;
 };
 
 struct Ctx {
   int device = -1;
   DevBuf tk, tv;                 // ping-pong partner of keys / values
-  DevBuf tasks[2], units, cm, leaf[3], copies, ctr, scratch;
+  DevBuf tasks[2], units, cm, leaf[LEAF_CLASSES], copies, ctr, scratch, lrn;
   std::vector<LevelKeep> lv;
   LevelCounters* h_ctr = nullptr;  // pinned
   void* h_stage = nullptr;         // pinned staging (task upload etc.)
   hipEvent_t done = nullptr;
   hipStream_t last_stream = nullptr;
   bool has_last = false;
+  std::vector<hipEvent_t> ev_pool;
+  struct Ctx* inner = nullptr;     // separate state for the sort of the learned partitioner's sample
 };
+
+// Per-kernel timing with HIP events on the sort's stream (opts->profile).
+struct Prof {
+  struct Rec {
+    int kind;
+    hipEvent_t a, b;
+    double bytes;
+  };
+  bool on = false;
+  hipStream_t s = nullptr;
+  Ctx* c = nullptr;
+  std::vector<Rec> recs;
+  Rec cur;
+  hipEvent_t ev() {
+    if (!c->ev_pool.empty()) {
+      hipEvent_t e = c->ev_pool.back();
+      c->ev_pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+  }
+  void begin(int kind) {
+    if (!on) return;
+    cur.kind = kind;
+    cur.a = ev();
+    cur.b = ev();
+    cur.bytes = 0;
+    (void)hipEventRecord(cur.a, s);
+  }
+  void end(double bytes) {
+    if (!on) return;
+    cur.bytes = bytes;
+    (void)hipEventRecord(cur.b, s);
+    recs.push_back(cur);
+  }
+  void finish(dtsort_stats* st) {
+    if (!on) return;
+    (void)hipStreamSynchronize(s);
+    for (const Rec& r : recs) {
+      float ms = 0;
+      (void)hipEventElapsedTime(&ms, r.a, r.b);
+      if (st) {
+        st->kernel_ms[r.kind] += ms;
+        st->kernel_bytes[r.kind] += r.bytes;
+        st->kernel_launches[r.kind] += 1;
+      }
+      c->ev_pool.push_back(r.a);
+      c->ev_pool.push_back(r.b);
+    }
+    recs.clear();
+  }
+};
+enum ProfKind { PK_PLAN = 0, PK_HIST, PK_SCAN, PK_SCATTER, PK_CHILDREN, PK_LEAF, PK_COPY, PK_MERGE };
 
 static std::mutex g_mu;
 static std::vector<Ctx*> g_ctx;
@@ -85,21 +143,28 @@ static int ensure(DevBuf& b, size_t bytes, hipStream_t s) {
   return 0;
 }
 
+static Ctx* new_ctx(int dev) {
+  Ctx* c = new Ctx();
+  c->device = dev;
+  c->lv.resize(MAX_LEVELS);
+  if (hipHostMalloc((void**)&c->h_ctr, sizeof(LevelCounters) * MAX_LEVELS) != hipSuccess ||
+      hipHostMalloc(&c->h_stage, 1 << 16) != hipSuccess ||
+      hipEventCreateWithFlags(&c->done, hipEventDisableTiming) != hipSuccess) {
+    (void)hipGetLastError();
+    delete c;
+    return nullptr;
+  }
+  return c;
+}
+
 static int get_ctx(Ctx** out) {
   int dev = 0;
   HIPCHK(hipGetDevice(&dev));
   std::lock_guard<std::mutex> lk(g_mu);
   if ((int)g_ctx.size() <= dev) g_ctx.resize(dev + 1, nullptr);
   if (!g_ctx[dev]) {
-    Ctx* c = new Ctx();
-    c->device = dev;
-    c->lv.resize(MAX_LEVELS);
-    if (hipHostMalloc((void**)&c->h_ctr, sizeof(LevelCounters) * MAX_LEVELS) != hipSuccess ||
-        hipHostMalloc(&c->h_stage, 1 << 16) != hipSuccess || hipEventCreateWithFlags(&c->done, hipEventDisableTiming) != hipSuccess) {
-      (void)hipGetLastError();
-      delete c;
-      return fail(DTSORT_ENOMEM, "pinned host allocation failed");
-    }
+    Ctx* c = new_ctx(dev);
+    if (!c) return fail(DTSORT_ENOMEM, "pinned host allocation failed");
     g_ctx[dev] = c;
   }
   *out = g_ctx[dev];
@@ -155,6 +220,83 @@ static void fill_caps(LevelArgs& a, uint32_t n_tasks, uint64_t total, int gmax, 
   a.caps.spills = (uint32_t)(total / (1u << 20) + a.caps.merges + 1);
 }
 
+struct LearnedInfoH {
+  float bal_learned, bal_digit;
+  uint32_t use_learned;
+  uint32_t light_held;
+  float final_loss;
+  uint32_t pad;
+};
+
+constexpr uint32_t LEARN_SAMPLE = 1u << 16;  // training sample (sorted by the method itself)
+constexpr uint32_t LEARN_HELD = 1u << 14;    // held-out sample for the balance judge
+
+// Learned root plan (LEARNED mode, root task already planned by the sampling
+// step): draw and sort the training sample, train the CDF model, derive the
+// splitters, and let the judge keep whichever zones balance the held-out
+// sample better.  Everything stays on the device; `info` receives the verdict.
+template <typename K, typename V>
+static int learned_root(Ctx* c, SortJob<K, V>& J, LevelArgs& a, hipStream_t s, void* info) {
+  const dtsort_opts& o = J.o;
+  const int steps = o.learned_steps > 0 ? o.learned_steps : 256;
+  uint32_t batch = o.learned_batch > 0 ? (uint32_t)o.learned_batch : 1024u;
+  batch = std::min(batch, LEARN_SAMPLE);
+  const float lr = o.learned_lr > 0 ? o.learned_lr : 3e-3f;
+  const uint32_t N = LEARN_SAMPLE, HN = LEARN_HELD;
+  const size_t nwg = (batch + MLP_GT - 1) / MLP_GT;
+  size_t off = 0;
+  auto carve = [&](size_t bytes) {
+    size_t o2 = off;
+    off += (bytes + 255) & ~(size_t)255;
+    return o2;
+  };
+  const size_t o_s = carve(sizeof(K) * N), o_h = carve(sizeof(K) * HN), o_x = carve(4 * N), o_y = carve(4 * N),
+               o_p = carve(4 * N), o_mono = carve(4 * N), o_par = carve(4 * MLP_PARAMS), o_m = carve(4 * MLP_PARAMS),
+               o_v = carve(4 * MLP_PARAMS), o_part = carve(4 * (MLP_PARAMS + 1) * nwg), o_l = carve(4 * (size_t)steps),
+               o_spl = carve(8 << GMAX);
+  int r;
+  if ((r = ensure(c->lrn, off, s))) return r;
+  char* base = (char*)c->lrn.p;
+  K* samp = (K*)(base + o_s);
+  K* held = (K*)(base + o_h);
+  float* x = (float*)(base + o_x);
+  float* y = (float*)(base + o_y);
+  float* pred = (float*)(base + o_p);
+  float* mono = (float*)(base + o_mono);
+  float* par = (float*)(base + o_par);
+  float* m = (float*)(base + o_m);
+  float* v = (float*)(base + o_v);
+  float* part = (float*)(base + o_part);
+  float* losses = (float*)(base + o_l);
+  uint64_t* spl = (uint64_t*)(base + o_spl);
+  learned_kernels_draw<K>(J.bufs.k[0], J.n, o.seed, 0x4C52u, N, samp, s);
+  learned_kernels_draw<K>(J.bufs.k[0], J.n, o.seed, 0x4C48u, HN, held, s);
+  HIPCHK(hipGetLastError());
+  // the training sample is sorted by the method itself, on separate state
+  if (!c->inner) {
+    c->inner = new_ctx(c->device);
+    if (!c->inner) return fail(DTSORT_ENOMEM, "pinned host allocation failed");
+  }
+  SortJob<K, NoVal> J2;
+  J2.n = N;
+  J2.seg = nullptr;
+  J2.n_seg = 0;
+  J2.key_bits = J.key_bits;
+  dtsort_default_opts(&J2.o);
+  J2.o.seed = o.seed;
+  if ((r = ensure(c->inner->tk, dtsort_workspace_bytes((int)sizeof(K), 0, N), s))) return r;
+  J2.bufs.k[0] = samp;
+  J2.bufs.k[1] = (K*)c->inner->tk.p;
+  if ((r = run_sort<K, NoVal>(c->inner, J2, s, nullptr))) return r;
+  mlp_data<K>(samp, N, J.key_bits, x, y, s);
+  mlp_train(x, y, N, o.seed, steps, batch, lr, par, m, v, part, losses, s);
+  mlp_forward(par, x, N, pred, s);
+  learned_kernels_split<K>(samp, pred, N, 1u << plan_gamma((uint32_t)J.n, a.g_override), mono, spl, s);
+  learned_kernels_judge<K>(a.tasks, a.tab, held, HN, spl, info, losses, steps, s);
+  HIPCHK(hipGetLastError());
+  return 0;
+}
+
 template <typename K, typename V>
 static int run_sort(Ctx* c, SortJob<K, V>& J, hipStream_t s, dtsort_stats* stats) {
   constexpr bool HV = HasVal<V>::value;
@@ -173,16 +315,22 @@ static int run_sort(Ctx* c, SortJob<K, V>& J, hipStream_t s, dtsort_stats* stats
   a.seed = o.seed;
   a.g_override = gover;
   a.cutoff = cutoff;
-  a.leaf_max[0] = leaf_cap<K, V>(0);
-  a.leaf_max[1] = leaf_cap<K, V>(1);
-  a.leaf_max[2] = leaf_cap<K, V>(2);
+  for (int k = 0; k < LEAF_CLASSES; ++k) a.leaf_max[k] = leaf_cap<K, V>(k);
   a.plain = o.mode == DTSORT_MODE_PLAIN;
   a.key_bits = J.key_bits;
   if (stats) std::memset(stats, 0, sizeof(*stats));
 
   int r;
-  if ((r = ensure(c->ctr, sizeof(LevelCounters) * MAX_LEVELS, s))) return r;
+  if ((r = ensure(c->ctr, sizeof(LevelCounters) * MAX_LEVELS + 256, s))) return r;
   LevelCounters* dctr = (LevelCounters*)c->ctr.p;
+  void* d_info = (char*)c->ctr.p + sizeof(LevelCounters) * MAX_LEVELS;
+  Prof prof;
+  prof.on = o.profile != 0 && stats != nullptr;
+  prof.s = s;
+  prof.c = c;
+  const double rec_bytes = (double)sizeof(K) + (HV ? (double)sizeof(V) : 0.0);
+  const bool learned = o.mode == DTSORT_MODE_LEARNED && !J.seg && n >= (1u << 20);
+  hipEvent_t le0 = nullptr, le1 = nullptr;
 
   uint32_t n_tasks = 0;
   uint64_t total = 0;
@@ -199,11 +347,11 @@ static int run_sort(Ctx* c, SortJob<K, V>& J, hipStream_t s, dtsort_stats* stats
     a.caps.leaf = J.n_seg + 1;
     a.caps.copies = J.n_seg + 1;
     if ((r = ensure(c->tasks[cur], sizeof(Task) * (size_t)a.caps.tasks, s))) return r;
-    for (int k = 0; k < 3; ++k)
+    for (int k = 0; k < LEAF_CLASSES; ++k)
       if ((r = ensure(c->leaf[k], sizeof(Leaf) * (size_t)a.caps.leaf, s))) return r;
     if ((r = ensure(c->copies, sizeof(Leaf) * (size_t)a.caps.copies, s))) return r;
     a.next = (Task*)c->tasks[cur].p;
-    for (int k = 0; k < 3; ++k) a.leaf[k] = (Leaf*)c->leaf[k].p;
+    for (int k = 0; k < LEAF_CLASSES; ++k) a.leaf[k] = (Leaf*)c->leaf[k].p;
     a.copies = (Leaf*)c->copies.p;
     a.ctr = dctr;
     HIPCHK(hipMemsetAsync(dctr, 0, sizeof(LevelCounters), s));
@@ -214,9 +362,14 @@ static int run_sort(Ctx* c, SortJob<K, V>& J, hipStream_t s, dtsort_stats* stats
     const LevelCounters h = c->h_ctr[0];
     if (h.error & ERR_SEGMENTS) return fail(DTSORT_EINVAL, "segment offsets are not valid");
     if (h.error) return fail(DTSORT_EINTERNAL, "capacity check failed while seeding segments");
-    for (int k = 0; k < 3; ++k) launch_leaf<K, V>((Leaf*)c->leaf[k].p, h.leaf[k], k, J.bufs, s);
+    prof.begin(PK_LEAF);
+    for (int k = 0; k < LEAF_CLASSES; ++k) launch_leaf<K, V>((Leaf*)c->leaf[k].p, h.leaf[k], k, J.bufs, s);
+    prof.end(2.0 * rec_bytes * (double)h.st_leaf_records);
     HIPCHK(hipGetLastError());
-    if (stats) stats->leaf_sorts += h.leaf[0] + h.leaf[1] + h.leaf[2], stats->records_leaf_sorted += h.st_leaf_records;
+    if (stats) {
+      for (int k = 0; k < LEAF_CLASSES; ++k) stats->leaf_sorts += h.leaf[k];
+      stats->records_leaf_sorted += h.st_leaf_records;
+    }
     n_tasks = h.next_tasks;
     total = h.next_records;
     max_size = h.next_max_size;
@@ -235,7 +388,9 @@ static int run_sort(Ctx* c, SortJob<K, V>& J, hipStream_t s, dtsort_stats* stats
       hl->to = 0;
       hl->pad = 0;
       HIPCHK(hipMemcpyAsync(c->leaf[0].p, hl, sizeof(Leaf), hipMemcpyHostToDevice, s));
-      const int cls = n <= leaf_cap<K, V>(0) ? 0 : (n <= leaf_cap<K, V>(1) ? 1 : 2);
+      int cls = LEAF_CLASSES - 1;
+      for (int k = LEAF_CLASSES - 2; k >= 0; --k)
+        if (n <= leaf_cap<K, V>(k)) cls = k;
       launch_leaf<K, V>((Leaf*)c->leaf[0].p, 1, cls, J.bufs, s);
       HIPCHK(hipGetLastError());
       if (stats) stats->leaf_sorts = 1, stats->records_leaf_sorted = n;
@@ -254,6 +409,7 @@ static int run_sort(Ctx* c, SortJob<K, V>& J, hipStream_t s, dtsort_stats* stats
     ht->tgt = 0;
     ht->flags = 0;
     ht->gamma = (uint8_t)plan_gamma((uint32_t)n, gover);
+    (void)learned;
     HIPCHK(hipMemcpyAsync(c->tasks[cur].p, ht, sizeof(Task), hipMemcpyHostToDevice, s));
     n_tasks = 1;
     total = n;
@@ -269,9 +425,11 @@ static int run_sort(Ctx* c, SortJob<K, V>& J, hipStream_t s, dtsort_stats* stats
     uint64_t chunk = (total + 2047) / 2048;
     chunk = std::max<uint64_t>(8192, (chunk + 8191) / 8192 * 8192);
     const uint64_t units = total / chunk + n_tasks + 1;
-    const SlotLayout sl = slot_layout(gmax, false);
+    const bool learn_here = learned && L == 0;
+    const SlotLayout sl = slot_layout(gmax, learn_here);
     const uint64_t tab_bytes = (uint64_t)n_tasks * sl.bytes;
-    const uint64_t cm_entries = units * (uint64_t)nb_cap(gmax);
+    const uint32_t cols = dist_cols(gmax);
+    const uint64_t cm_entries = units * cols * (uint64_t)nb_cap(gmax);
     LevelKeep& K_ = c->lv[L];
     fill_caps<K, V>(a, n_tasks, total, gmax, cutoff);
     a.caps.units = (uint32_t)units;
@@ -281,7 +439,7 @@ static int run_sort(Ctx* c, SortJob<K, V>& J, hipStream_t s, dtsort_stats* stats
     if ((r = ensure(c->cm, 4 * cm_entries, s))) return r;
     if ((r = ensure(K_.tab, tab_bytes, s))) return r;
     if ((r = ensure(c->tasks[1 - cur], sizeof(Task) * (size_t)a.caps.tasks, s))) return r;
-    for (int k = 0; k < 3; ++k)
+    for (int k = 0; k < LEAF_CLASSES; ++k)
       if ((r = ensure(c->leaf[k], sizeof(Leaf) * (size_t)a.caps.leaf, s))) return r;
     if ((r = ensure(c->copies, sizeof(Leaf) * (size_t)a.caps.copies, s))) return r;
     if ((r = ensure(K_.merges, sizeof(Merge) * (size_t)a.caps.merges, s))) return r;
@@ -293,29 +451,67 @@ static int run_sort(Ctx* c, SortJob<K, V>& J, hipStream_t s, dtsort_stats* stats
     a.units = (uint2*)c->units.p;
     a.tab = (uint8_t*)K_.tab.p;
     a.slot_bytes = sl.bytes;
+    a.cols = cols;
     a.cm = (uint32_t*)c->cm.p;
     a.next = (Task*)c->tasks[1 - cur].p;
-    for (int k = 0; k < 3; ++k) a.leaf[k] = (Leaf*)c->leaf[k].p;
+    for (int k = 0; k < LEAF_CLASSES; ++k) a.leaf[k] = (Leaf*)c->leaf[k].p;
     a.copies = (Leaf*)c->copies.p;
     a.merges = (Merge*)K_.merges.p;
     a.spills = (Leaf*)K_.spills.p;
     a.ctr = dctr + L;
     HIPCHK(hipMemsetAsync(a.ctr, 0, sizeof(LevelCounters), s));
     launch_prep(a, s);
+    prof.begin(PK_PLAN);
     launch_plan<K>(a, J.bufs.k[0], J.bufs.k[1], s);
+    prof.end(0.0);
+    if (learn_here) {
+      HIPCHK(hipEventCreate(&le0));
+      HIPCHK(hipEventCreate(&le1));
+      HIPCHK(hipEventRecord(le0, s));
+      if ((r = learned_root<K, V>(c, J, a, s, d_info))) return r;
+      HIPCHK(hipEventRecord(le1, s));
+    }
     const uint32_t max_chunks = (uint32_t)(max_size / chunk + 1);
-    launch_distribute<K, V>(a, J.bufs, gmax, max_chunks, s);
+    prof.begin(PK_HIST);
+    launch_distribute<K, V>(a, J.bufs, gmax, max_chunks, s, 0);
+    prof.end((double)sizeof(K) * (double)total);
+    prof.begin(PK_SCAN);
+    launch_distribute<K, V>(a, J.bufs, gmax, max_chunks, s, 1);
+    prof.end(8.0 * (double)cm_entries);
+    prof.begin(PK_SCATTER);
+    launch_distribute<K, V>(a, J.bufs, gmax, max_chunks, s, 2);
+    prof.end(2.0 * rec_bytes * (double)total);
+    prof.begin(PK_CHILDREN);
     launch_children<K, V>(a, J.bufs, s);
+    prof.end(0.0);
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(c->h_ctr + L, a.ctr, sizeof(LevelCounters), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     const LevelCounters h = c->h_ctr[L];
     if (h.error) return fail(DTSORT_EINTERNAL, "device capacity check failed (flags " + std::to_string(h.error) + ")");
-    for (int k = 0; k < 3; ++k) launch_leaf<K, V>((Leaf*)c->leaf[k].p, h.leaf[k], k, J.bufs, s);
+    if (learn_here && stats) {
+      LearnedInfoH li;
+      HIPCHK(hipMemcpy(&li, d_info, sizeof(li), hipMemcpyDeviceToHost));
+      float ms = 0;
+      HIPCHK(hipEventElapsedTime(&ms, le0, le1));
+      stats->learned_used = (int32_t)li.use_learned;
+      stats->learned_balance = li.bal_learned;
+      stats->sampling_balance = li.bal_digit;
+      stats->learned_final_loss = li.final_loss;
+      stats->learned_ms = ms;
+    }
+    if (le0) (void)hipEventDestroy(le0), le0 = nullptr;
+    if (le1) (void)hipEventDestroy(le1), le1 = nullptr;
+    prof.begin(PK_LEAF);
+    for (int k = 0; k < LEAF_CLASSES; ++k) launch_leaf<K, V>((Leaf*)c->leaf[k].p, h.leaf[k], k, J.bufs, s);
+    prof.end(2.0 * rec_bytes * (double)h.st_leaf_records);
+    prof.begin(PK_COPY);
     launch_copy<K, V>((Leaf*)c->copies.p, h.copies, J.bufs, s);
+    prof.end(2.0 * rec_bytes * (double)h.st_copy_records);
     K_.n_merges = h.merges;
     K_.n_munits = h.merge_units;
     K_.n_spills = h.spills;
+    K_.merge_records = (double)h.st_merge_records;
     launch_merge_units((Merge*)K_.merges.p, h.merges, (uint2*)K_.munits.p, s);
     HIPCHK(hipGetLastError());
     if (stats) {
@@ -326,7 +522,7 @@ static int run_sort(Ctx* c, SortJob<K, V>& J, hipStream_t s, dtsort_stats* stats
       stats->heavy_records += h.st_heavy_records;
       stats->merges += h.merges;
       stats->records_merged += h.st_merge_records;
-      stats->leaf_sorts += h.leaf[0] + h.leaf[1] + h.leaf[2];
+      for (int k = 0; k < LEAF_CLASSES; ++k) stats->leaf_sorts += h.leaf[k];
       stats->records_leaf_sorted += h.st_leaf_records;
       stats->records_copied += h.st_copy_records;
       stats->overflow_records += h.st_overflow_records;
@@ -340,11 +536,14 @@ static int run_sort(Ctx* c, SortJob<K, V>& J, hipStream_t s, dtsort_stats* stats
   for (int l = L - 1; l >= 0; --l) {
     LevelKeep& K_ = c->lv[l];
     if (K_.n_merges == 0) continue;
+    prof.begin(PK_MERGE);
     launch_copy<K, V>((Leaf*)K_.spills.p, K_.n_spills, J.bufs, s);
     launch_merge<K, V>((Merge*)K_.merges.p, K_.n_merges, (uint2*)K_.munits.p, K_.n_munits, (uint8_t*)K_.tab.p,
                        J.bufs, s);
+    prof.end(2.0 * rec_bytes * K_.merge_records);
     HIPCHK(hipGetLastError());
   }
+  prof.finish(stats);
   return 0;
 }
 
@@ -464,6 +663,28 @@ void dtsort_release(void) {
       free_buf(l.merges);
       free_buf(l.munits);
       free_buf(l.spills);
+    }
+    free_buf(c->lrn);
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    if (c->inner) {
+      Ctx* in = c->inner;
+      free_buf(in->tk);
+      for (auto& b : in->tasks) free_buf(b);
+      free_buf(in->units);
+      free_buf(in->cm);
+      for (auto& b : in->leaf) free_buf(b);
+      free_buf(in->copies);
+      free_buf(in->ctr);
+      for (auto& l : in->lv) {
+        free_buf(l.tab);
+        free_buf(l.merges);
+        free_buf(l.munits);
+        free_buf(l.spills);
+      }
+      if (in->h_ctr) (void)hipHostFree(in->h_ctr);
+      if (in->h_stage) (void)hipHostFree(in->h_stage);
+      if (in->done) (void)hipEventDestroy(in->done);
+      delete in;
     }
     if (c->h_ctr) (void)hipHostFree(c->h_ctr);
     if (c->h_stage) (void)hipHostFree(c->h_stage);

@@ -353,3 +353,239 @@ int dtsort_mlp_train_u64(const uint64_t* sorted_keys, size_t n, uint64_t seed, i
 }
 
 }  // extern "C"
+
+// ====================================================================
+// Learned root plan: training sample, splitters, balance judge, tables.
+// ====================================================================
+namespace dts {
+
+// Sample keys at counter-based random positions (the same generator as the
+// sampling step, with its own stream tag).
+template <typename K>
+__global__ void k_draw(const K* keys, uint64_t n, uint64_t seed, uint32_t tag, uint32_t count, K* out) {
+  const uint64_t sb = sample_base(seed, 0, tag);
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
+    const uint64_t r = mix64(sb + (uint64_t)(i + 1) * GOLD);
+    out[i] = keys[__umul64hi(r, n)];
+  }
+}
+
+// Splitters from the model: running maximum of the predictions over the
+// sorted sample, then for every zone boundary b/Z the first sample key whose
+// monotone prediction reaches it (one past the largest key if none does),
+// made non-decreasing.  One workgroup.
+template <typename K>
+__global__ __launch_bounds__(1024) void k_splitters(const K* sk, const float* pred, uint32_t n, uint32_t zones,
+                                                    float* mono, uint64_t* spl) {
+  __shared__ float wmax[16];
+  __shared__ float carry;
+  const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+  if (threadIdx.x == 0) carry = -INFINITY;
+  __syncthreads();
+  for (uint32_t b0 = 0; b0 < n; b0 += 1024) {
+    const uint32_t i = b0 + threadIdx.x;
+    float x = i < n ? pred[i] : -INFINITY;
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+      const float y = __shfl_up(x, o, WAVE);
+      if (lane >= o) x = fmaxf(x, y);
+    }
+    if (lane == WAVE - 1) wmax[wv] = x;
+    __syncthreads();
+    float pre = carry;
+    for (int w = 0; w < wv; ++w) pre = fmaxf(pre, wmax[w]);
+    x = fmaxf(x, pre);
+    if (i < n) mono[i] = x;
+    __syncthreads();
+    if (threadIdx.x == 1023) carry = x;
+    __syncthreads();
+  }
+  const uint64_t top = (uint64_t)(K)~(K)0;
+  for (uint32_t b = threadIdx.x + 1; b < zones; b += 1024) {
+    const float q = (float)b / (float)zones;
+    uint32_t lo = 0, m = n;
+    while (m > 0) {
+      const uint32_t half = m >> 1;
+      if (mono[lo + half] < q) {
+        lo += half + 1;
+        m -= half + 1;
+      } else {
+        m = half;
+      }
+    }
+    uint64_t s;
+    if (lo < n) {
+      s = (uint64_t)sk[lo];
+    } else {
+      const uint64_t mx = (uint64_t)sk[n - 1];
+      s = mx < top ? mx + 1 : top;
+    }
+    spl[b - 1] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t last = 0;
+    for (uint32_t b = 0; b + 1 < zones; ++b) {
+      last = spl[b] > last ? spl[b] : last;
+      spl[b] = last;
+    }
+  }
+}
+
+struct LearnedInfo {
+  float bal_learned, bal_digit;
+  uint32_t use_learned;
+  uint32_t light_held;
+  float final_loss;
+  uint32_t pad;
+};
+
+// Judge: bucket-balance error (largest zone / ideal) of the light held-out
+// keys under the digit plan already in the slot and under the splitters; the
+// model's zones are used only when strictly better.  Then, if used, rewrite
+// the task's light-id table for splitter zones (heavy keys are the sampling
+// detector's) and mark the task.
+template <typename K>
+__global__ __launch_bounds__(1024) void k_judge_apply(Task* task, uint8_t* tab, const K* held, uint32_t nh_keys,
+                                                      const uint64_t* spl_in, LearnedInfo* info,
+                                                      const float* losses, int steps) {
+  __shared__ uint32_t cd[1 << GMAX], cl[1 << GMAX];
+  __shared__ uint32_t hz[1 << (GMAX - 1)];
+  __shared__ K H[1 << (GMAX - 1)];
+  __shared__ K SPL[1 << GMAX];
+  __shared__ uint32_t light_cnt;
+  __shared__ int use;
+  Task t = *task;
+  const int g = t.gamma;
+  const uint32_t Z = 1u << g;
+  const SlotLayout sl = slot_layout(g, true);
+  uint8_t* slot = tab + t.tab_off;
+  uint32_t* gL = (uint32_t*)(slot + sl.light);
+  const uint64_t* gH = (const uint64_t*)(slot + sl.heavy);
+  uint64_t* gS = (uint64_t*)(slot + sl.spl);
+  for (uint32_t i = threadIdx.x; i < Z; i += 1024) {
+    cd[i] = 0;
+    cl[i] = 0;
+  }
+  for (uint32_t i = threadIdx.x; i < t.n_heavy; i += 1024) H[i] = (K)gH[i];
+  for (uint32_t i = threadIdx.x; i + 1 < Z; i += 1024) SPL[i] = (K)spl_in[i];
+  if (threadIdx.x == 0) light_cnt = 0;
+  __syncthreads();
+  const K mhi = mask_below<K>(t.hi);
+  const uint32_t zd = 1u << t.w;
+  for (uint32_t i = threadIdx.x; i < nh_keys; i += 1024) {
+    const K k = held[i];
+    // heavy keys are excluded from the balance
+    uint32_t lo = 0, m = t.n_heavy;
+    while (m > 0) {
+      const uint32_t half = m >> 1;
+      if (H[lo + half] < k) {
+        lo += half + 1;
+        m -= half + 1;
+      } else {
+        m = half;
+      }
+    }
+    if (lo < t.n_heavy && H[lo] == k) continue;
+    atomicAdd(&light_cnt, 1u);
+    const K low = k & mhi;
+    if (t.top >= t.hi || shr<K>(low, t.top) == 0) {
+      const uint32_t z = (uint32_t)(shr<K>(low, t.shift) & (K)(zd - 1u));
+      atomicAdd(&cd[z], 1u);
+    }
+    uint32_t a = 0, n2 = Z - 1;
+    while (n2 > 0) {
+      const uint32_t half = n2 >> 1;
+      if (SPL[a + half] <= k) {
+        a += half + 1;
+        n2 -= half + 1;
+      } else {
+        n2 = half;
+      }
+    }
+    atomicAdd(&cl[a], 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t md = 0, ml = 0;
+    for (uint32_t z = 0; z < zd; ++z) md = max(md, cd[z]);
+    for (uint32_t z = 0; z < Z; ++z) ml = max(ml, cl[z]);
+    const float lc = (float)max(light_cnt, 1u);
+    const float bd = (float)md / (lc / (float)zd);
+    const float bl = (float)ml / (lc / (float)Z);
+    info->bal_digit = bd;
+    info->bal_learned = bl;
+    info->light_held = light_cnt;
+    info->final_loss = steps > 0 ? losses[steps - 1] : 0.0f;
+    use = bl < bd;
+    info->use_learned = use;
+  }
+  __syncthreads();
+  if (!use) return;
+  // zones of the heavy keys under the splitters, then light ids
+  for (uint32_t i = threadIdx.x; i < t.n_heavy; i += 1024) {
+    const K k = H[i];
+    uint32_t a = 0, n2 = Z - 1;
+    while (n2 > 0) {
+      const uint32_t half = n2 >> 1;
+      if (SPL[a + half] <= k) {
+        a += half + 1;
+        n2 -= half + 1;
+      } else {
+        n2 = half;
+      }
+    }
+    hz[i] = a;
+  }
+  for (uint32_t i = threadIdx.x; i + 1 < Z; i += 1024) gS[i] = (uint64_t)SPL[i];
+  __syncthreads();
+  for (uint32_t z = threadIdx.x; z <= Z; z += 1024) {
+    uint32_t lo = 0, m = t.n_heavy;
+    while (m > 0) {
+      const uint32_t half = m >> 1;
+      if (hz[lo + half] < z) {
+        lo += half + 1;
+        m -= half + 1;
+      } else {
+        m = half;
+      }
+    }
+    gL[z] = z + lo;
+  }
+  if (threadIdx.x == 0) {
+    t.flags |= TF_LEARNED;
+    t.w = (uint8_t)g;
+    t.shift = 0;
+    t.top = t.hi;
+    t.n_buckets = (uint16_t)(Z + t.n_heavy + 1);
+    *task = t;
+  }
+}
+
+template <typename K>
+void learned_kernels_draw(const K* keys, uint64_t n, uint64_t seed, uint32_t tag, uint32_t count, K* out,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_draw<K>, dim3((count + 255) / 256), dim3(256), 0, s, keys, n, seed, tag, count, out);
+}
+template <typename K>
+void learned_kernels_split(const K* sk, const float* pred, uint32_t n, uint32_t zones, float* mono, uint64_t* spl,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_splitters<K>, dim3(1), dim3(1024), 0, s, sk, pred, n, zones, mono, spl);
+}
+template <typename K>
+void learned_kernels_judge(Task* task, uint8_t* tab, const K* held, uint32_t nh, const uint64_t* spl, void* info,
+                           const float* losses, int steps, hipStream_t s) {
+  hipLaunchKernelGGL(k_judge_apply<K>, dim3(1), dim3(1024), 0, s, task, tab, held, nh, spl, (LearnedInfo*)info,
+                     losses, steps);
+}
+#define DTS_INST(K)                                                                                           \
+  template void learned_kernels_draw<K>(const K*, uint64_t, uint64_t, uint32_t, uint32_t, K*, hipStream_t);   \
+  template void learned_kernels_split<K>(const K*, const float*, uint32_t, uint32_t, float*, uint64_t*,      \
+                                         hipStream_t);                                                       \
+  template void learned_kernels_judge<K>(Task*, uint8_t*, const K*, uint32_t, const uint64_t*, void*,        \
+                                         const float*, int, hipStream_t);
+DTS_INST(uint32_t)
+DTS_INST(uint64_t)
+#undef DTS_INST
+
+}  // namespace dts

@@ -144,7 +144,15 @@ __global__ __launch_bounds__(T) void k_leaf(const Leaf* items, Bufs<K, V> bf) {
   __shared__ K sk[N];
   __shared__ uint16_t si[HV ? N : 1];
   __shared__ uint32_t cnt[bsort_cnt_words<T>()];
+  // LDS-match ranking when its tables fit next to the keys, else ballot ranking
+  constexpr bool USE_LDS = N * sizeof(K) + (HV ? N * 2 : 0) + 4 * bsort_cnt_words<T>() +
+                               8 * bsort_match_words<T>() <= 150 * 1024;
+  constexpr int RANK = USE_LDS ? RANK_LDS : RANK_BALLOT;
+  __shared__ unsigned long long mk[USE_LDS ? bsort_match_words<T>() : 1];
   __shared__ K red[2 * (T / WAVE)];
+  if constexpr (USE_LDS) {
+    for (int i = threadIdx.x; i < bsort_match_words<T>(); i += T) mk[i] = 0ull;
+  }
   const Leaf it = items[blockIdx.x];
   const K* kin = bf.k[it.from] + it.off;
   K* kout = bf.k[it.to] + it.off;
@@ -161,7 +169,7 @@ __global__ __launch_bounds__(T) void k_leaf(const Leaf* items, Bufs<K, V> bf) {
   block_or_and<K, T, ITEMS>(kk, n, red, &vor, &vand);
   const K diff = (vor ^ vand) & mask_below<K>(it.bits);
   if (diff) {
-    block_radix_sort<K, T, ITEMS, HV>(kk, ix, trailing_zeros(diff), bit_length(diff), sk, si, cnt);
+    block_radix_sort<K, T, ITEMS, HV, RANK>(kk, ix, trailing_zeros(diff), bit_length(diff), sk, si, cnt, mk);
   }
 #pragma unroll
   for (int i = 0; i < ITEMS; ++i) {
@@ -192,10 +200,12 @@ void launch_leaf(const Leaf* items, uint32_t n_items, int cls, Bufs<K, V> b, hip
   if (n_items == 0) return;
   constexpr bool big8 = sizeof(K) == 8 && HasVal<V>::value;
   if (cls == 0) {
-    hipLaunchKernelGGL((k_leaf<K, V, 256, 8>), dim3(n_items), dim3(256), 0, s, items, b);
+    hipLaunchKernelGGL((k_leaf<K, V, 256, 4>), dim3(n_items), dim3(256), 0, s, items, b);
+  } else if (cls == 1) {
+    hipLaunchKernelGGL((k_leaf<K, V, 256, 16>), dim3(n_items), dim3(256), 0, s, items, b);
   } else if constexpr (big8) {
     hipLaunchKernelGGL((k_leaf<K, V, 512, 16>), dim3(n_items), dim3(512), 0, s, items, b);
-  } else if (cls == 1) {
+  } else if (cls == 2) {
     hipLaunchKernelGGL((k_leaf<K, V, 512, 16>), dim3(n_items), dim3(512), 0, s, items, b);
   } else {
     hipLaunchKernelGGL((k_leaf<K, V, 1024, 16>), dim3(n_items), dim3(1024), 0, s, items, b);

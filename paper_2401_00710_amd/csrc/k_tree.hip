@@ -20,92 +20,202 @@ namespace dts {
 constexpr uint32_t COPY_PIECE = 1u << 20;   // records per copy item
 constexpr uint32_t MERGE_TILE = 4096;       // outputs per gather unit
 
-template <typename K, typename V>
-__device__ inline void emit_child(const LevelArgs& a, uint64_t off, uint32_t c, int hi, int buf, int tgt, bool skip,
-                                  uint32_t n_root, uint32_t level) {
-  LevelCounters* ctr = a.ctr;
-  if (c == 0) return;
-  if (c == 1 || hi == 0) {
-    // finished: all keys equal (or a single record); move it if needed
-    if (buf != tgt) {
-      for (uint32_t p = 0; p < c; p += COPY_PIECE) {
-        const uint32_t i = atomicAdd(&ctr->copies, 1u);
-        if (i >= a.caps.copies) {
-          atomicOr(&ctr->error, ERR_COPY);
-          return;
-        }
-        Leaf l;
-        l.off = off + p;
-        l.size = min(COPY_PIECE, c - p);
-        l.bits = 0;
-        l.from = (uint8_t)buf;
-        l.to = (uint8_t)tgt;
-        l.pad = 0;
-        a.copies[i] = l;
+// Kinds of work a finished distribution hands on (one output list each).
+enum Kind : int { KD_TASK = 0, KD_LEAF0 = 1, KD_COPY = 5, KD_MERGE = 6, KD_MUNIT = 7, KD_SPILL = 8, KD_N = 9 };
+
+struct Child {
+  uint64_t off;
+  uint32_t c;
+  uint8_t hi, buf, tgt, skip;
+  int kind;        // -1: nothing to do
+  uint32_t slot;   // offset within the workgroup's reservation for `kind`
+};
+
+// What happens to a bucket of c records whose keys share every bit at and
+// above `hi`, lying in buffer `buf`, to end sorted in buffer `tgt`.
+__device__ inline int child_kind(const LevelArgs& a, uint32_t c, int hi, int buf, int tgt, uint32_t* units) {
+  *units = 1;
+  if (c == 0) return -1;
+  if (c == 1 || hi == 0) {  // finished: one record or all keys equal
+    if (buf == tgt) return -1;
+    *units = (c + COPY_PIECE - 1) / COPY_PIECE;
+    return KD_COPY;
+  }
+  if (c <= a.cutoff) {
+    int cls = LEAF_CLASSES - 1;
+    for (int k = LEAF_CLASSES - 2; k >= 0; --k)
+      if (c <= a.leaf_max[k]) cls = k;
+    return KD_LEAF0 + cls;
+  }
+  return KD_TASK;
+}
+
+__device__ inline uint32_t* kind_counter(LevelCounters* ctr, int kind) {
+  if (kind == KD_TASK) return &ctr->next_tasks;
+  if (kind >= KD_LEAF0 && kind < KD_LEAF0 + LEAF_CLASSES) return &ctr->leaf[kind - KD_LEAF0];
+  if (kind == KD_COPY) return &ctr->copies;
+  if (kind == KD_MERGE) return &ctr->merges;
+  if (kind == KD_MUNIT) return &ctr->merge_units;
+  return &ctr->spills;
+}
+
+__device__ inline uint32_t kind_cap(const LevelArgs& a, int kind) {
+  if (kind == KD_TASK) return a.caps.tasks;
+  if (kind >= KD_LEAF0 && kind < KD_LEAF0 + LEAF_CLASSES) return a.caps.leaf;
+  if (kind == KD_COPY) return a.caps.copies;
+  if (kind == KD_MERGE) return a.caps.merges;
+  if (kind == KD_MUNIT) return a.caps.munits;
+  return a.caps.spills;
+}
+
+__device__ inline void write_child(const LevelArgs& a, const Child& ch, uint32_t base, uint32_t n_root, uint32_t level,
+                                   int g_override) {
+  if (ch.kind < 0) return;
+  const uint32_t i = base + ch.slot;
+  if (ch.kind == KD_COPY) {
+    for (uint32_t p = 0, k = 0; p < ch.c; p += COPY_PIECE, ++k) {
+      if (i + k >= a.caps.copies) {
+        atomicOr(&a.ctr->error, ERR_COPY);
+        return;
       }
-      atomicAdd(&ctr->st_copy_records, (unsigned long long)c);
+      Leaf l;
+      l.off = ch.off + p;
+      l.size = min(COPY_PIECE, ch.c - p);
+      l.bits = 0;
+      l.from = ch.buf;
+      l.to = ch.tgt;
+      l.pad = 0;
+      a.copies[i + k] = l;
     }
     return;
   }
-  if (c <= a.cutoff) {
-    const int cls = c <= a.leaf_max[0] ? 0 : (c <= a.leaf_max[1] ? 1 : 2);
-    const uint32_t i = atomicAdd(&ctr->leaf[cls], 1u);
+  if (ch.kind >= KD_LEAF0 && ch.kind < KD_LEAF0 + LEAF_CLASSES) {
     if (i >= a.caps.leaf) {
-      atomicOr(&ctr->error, ERR_LEAF);
+      atomicOr(&a.ctr->error, ERR_LEAF);
       return;
     }
     Leaf l;
-    l.off = off;
-    l.size = c;
-    l.bits = (uint8_t)hi;
-    l.from = (uint8_t)buf;
-    l.to = (uint8_t)tgt;
+    l.off = ch.off;
+    l.size = ch.c;
+    l.bits = ch.hi;
+    l.from = ch.buf;
+    l.to = ch.tgt;
     l.pad = 0;
-    a.leaf[cls][i] = l;
-    atomicAdd(&ctr->st_leaf_records, (unsigned long long)c);
+    a.leaf[ch.kind - KD_LEAF0][i] = l;
     return;
   }
-  const uint32_t i = atomicAdd(&ctr->next_tasks, 1u);
+  // next-level task
   if (i >= a.caps.tasks) {
-    atomicOr(&ctr->error, ERR_TASKS);
+    atomicOr(&a.ctr->error, ERR_TASKS);
     return;
   }
   Task t;
-  t.off = off;
+  t.off = ch.off;
   t.cm_off = 0;
   t.tab_off = 0;
-  t.size = c;
+  t.size = ch.c;
   t.n_root = n_root;
   t.level = level;
   t.unit_base = 0;
   t.n_chunks = 0;
-  t.hi = (uint8_t)hi;
-  t.src = (uint8_t)buf;
-  t.tgt = (uint8_t)tgt;
-  t.flags = skip ? TF_SKIP_DISABLED : 0;
-  t.gamma = (uint8_t)plan_gamma(c, a.g_override);
+  t.hi = ch.hi;
+  t.src = ch.buf;
+  t.tgt = ch.tgt;
+  t.flags = ch.skip ? TF_SKIP_DISABLED : 0;
+  t.gamma = (uint8_t)plan_gamma(ch.c, g_override);
   t.w = 0;
   t.shift = 0;
   t.top = 0;
   t.n_heavy = 0;
   t.n_buckets = 0;
   a.next[i] = t;
-  atomicMax(&ctr->next_max_size, c);
-  atomicAdd(&ctr->next_records, c);
+}
+
+// Reserve this workgroup's ranges in every output list: LDS counters give
+// local offsets, then one global atomic per list.
+struct Reserve {
+  uint32_t cnt[KD_N];
+  uint32_t base[KD_N];
+  unsigned long long st_leaf, st_copy, st_heavy, st_merge, st_over;
+  uint32_t max_size, records;
+};
+
+__device__ inline uint32_t reserve_local(Reserve* r, int kind, uint32_t units) {
+  return atomicAdd(&r->cnt[kind], units);
+}
+
+__device__ inline void reserve_global(const LevelArgs& a, Reserve* r) {
+  if (threadIdx.x < KD_N) {
+    const int k = threadIdx.x;
+    r->base[k] = r->cnt[k] ? atomicAdd(kind_counter(a.ctr, k), r->cnt[k]) : 0u;
+    if (r->cnt[k] && r->base[k] + r->cnt[k] > kind_cap(a, k)) atomicOr(&a.ctr->error, ERR_TASKS << 16);
+  }
+  if (threadIdx.x == WAVE) {
+    LevelCounters* c = a.ctr;
+    if (r->st_leaf) atomicAdd(&c->st_leaf_records, r->st_leaf);
+    if (r->st_copy) atomicAdd(&c->st_copy_records, r->st_copy);
+    if (r->st_heavy) atomicAdd(&c->st_heavy_records, r->st_heavy);
+    if (r->st_merge) atomicAdd(&c->st_merge_records, r->st_merge);
+    if (r->st_over) atomicAdd(&c->st_overflow_records, r->st_over);
+    if (r->max_size) atomicMax(&c->next_max_size, r->max_size);
+    if (r->records) atomicAdd(&c->next_records, r->records);
+  }
+}
+
+__device__ inline void reserve_init(Reserve* r) {
+  if (threadIdx.x < KD_N) r->cnt[threadIdx.x] = 0;
+  if (threadIdx.x == 0) {
+    r->st_leaf = r->st_copy = r->st_heavy = r->st_merge = r->st_over = 0;
+    r->max_size = 0;
+    r->records = 0;
+  }
+}
+
+__device__ inline Child plan_child(const LevelArgs& a, Reserve* r, uint64_t off, uint32_t c, int hi, int buf, int tgt,
+                                   bool skip) {
+  Child ch;
+  ch.off = off;
+  ch.c = c;
+  ch.hi = (uint8_t)hi;
+  ch.buf = (uint8_t)buf;
+  ch.tgt = (uint8_t)tgt;
+  ch.skip = skip;
+  uint32_t units;
+  ch.kind = child_kind(a, c, hi, buf, tgt, &units);
+  ch.slot = 0;
+  if (ch.kind >= 0) {
+    ch.slot = reserve_local(r, ch.kind, units);
+    if (ch.kind == KD_COPY) atomicAdd(&r->st_copy, (unsigned long long)c);
+    if (ch.kind >= KD_LEAF0 && ch.kind < KD_LEAF0 + LEAF_CLASSES) atomicAdd(&r->st_leaf, (unsigned long long)c);
+    if (ch.kind == KD_TASK) {
+      atomicMax(&r->max_size, c);
+      atomicAdd(&r->records, c);
+    }
+  }
+  return ch;
 }
 
 // Batched form: every segment is the root of its own sort.
 template <typename K, typename V>
 __global__ __launch_bounds__(256) void k_seed(LevelArgs a, const uint64_t* seg, uint32_t n_seg, uint64_t n_total) {
+  __shared__ Reserve r;
+  reserve_init(&r);
+  __syncthreads();
   const uint32_t s = blockIdx.x * 256 + threadIdx.x;
-  if (s >= n_seg) return;
-  const uint64_t b = seg[s], e = seg[s + 1];
-  if (e < b || e > n_total || (s == 0 && b != 0) || (s + 1 == n_seg && e != n_total) || e - b >= (1ull << 32)) {
-    atomicOr(&a.ctr->error, ERR_SEGMENTS);
-    return;
+  Child ch;
+  ch.kind = -1;
+  if (s < n_seg) {
+    const uint64_t b = seg[s], e = seg[s + 1];
+    if (e < b || e > n_total || (s == 0 && b != 0) || (s + 1 == n_seg && e != n_total) || e - b >= (1ull << 32)) {
+      atomicOr(&a.ctr->error, ERR_SEGMENTS);
+    } else {
+      ch = plan_child(a, &r, b, (uint32_t)(e - b), a.key_bits, 0, 0, false);
+    }
   }
-  const uint32_t c = (uint32_t)(e - b);
-  emit_child<K, V>(a, b, c, a.key_bits, 0, 0, false, c, 0);
+  __syncthreads();
+  reserve_global(a, &r);
+  __syncthreads();
+  if (ch.kind >= 0) write_child(a, ch, r.base[ch.kind], ch.c, 0, a.g_override);
 }
 
 template <typename K, typename V>
@@ -115,12 +225,17 @@ void launch_seed_segments(const LevelArgs& a, const uint64_t* seg_off, uint32_t 
   hipLaunchKernelGGL((k_seed<K, V>), dim3((n_seg + 255) / 256), dim3(256), 0, s, a, seg_off, n_seg, n_total);
 }
 
-// Child planning: one workgroup per task, one thread per zone.
+// Child planning: one workgroup per task, one thread per zone (at most
+// 2^GMAX / 256 = 4 zones per thread, plus the overflow bucket on thread 0).
 template <typename K, typename V>
 __global__ __launch_bounds__(256) void k_children(LevelArgs a) {
+  constexpr int ZPT = (1 << GMAX) / 256;
+  constexpr bool HV = HasVal<V>::value;
+  __shared__ Reserve r;
   const Task t = a.tasks[blockIdx.x];
   if (t.n_chunks == 0) return;
-  constexpr bool HV = HasVal<V>::value;
+  reserve_init(&r);
+  __syncthreads();
   const bool learned = (t.flags & TF_LEARNED) != 0;
   const SlotLayout sl = slot_layout(t.gamma, learned);
   const uint8_t* slot = a.tab + t.tab_off;
@@ -129,8 +244,15 @@ __global__ __launch_bounds__(256) void k_children(LevelArgs a) {
   const uint64_t* SPL = (const uint64_t*)(slot + sl.spl);
   const int dst = 1 - t.src;
   const uint32_t zones = 1u << t.w;
-  unsigned long long heavy_recs = 0;
-  for (uint32_t z = threadIdx.x; z < zones; z += 256) {
+  Child ch[ZPT + 1];
+  Merge mg[ZPT];
+  uint32_t mslot[ZPT], uslot[ZPT], sslot[ZPT], spieces[ZPT];
+#pragma unroll
+  for (int k = 0; k < ZPT; ++k) {
+    ch[k].kind = -1;
+    mslot[k] = 0xFFFFFFFFu;
+    const uint32_t z = threadIdx.x + 256u * k;
+    if (z >= zones) continue;
     const uint32_t lid = L[z];
     const uint32_t m = L[z + 1] - lid - 1u;
     const uint32_t s0 = st[lid];
@@ -139,50 +261,32 @@ __global__ __launch_bounds__(256) void k_children(LevelArgs a) {
     if (m > 0) {
       ctgt = 1 - t.tgt;
       const uint32_t zend = st[lid + m + 1];
-      const uint32_t i = atomicAdd(&a.ctr->merges, 1u);
-      if (i >= a.caps.merges) {
-        atomicOr(&a.ctr->error, ERR_MERGE);
-      } else {
-        Merge mg;
-        mg.zone_off = t.off + s0;
-        mg.tab_off = t.tab_off;
-        mg.b0 = c0;
-        mg.m = m;
-        mg.hbase = lid - z;
-        mg.bstart = lid;
-        mg.zone_rel = s0;
-        const uint32_t zsize = zend - s0;
-        mg.n_units = (zsize + MERGE_TILE - 1) / MERGE_TILE;
-        mg.unit_base = atomicAdd(&a.ctr->merge_units, mg.n_units);
-        if (mg.unit_base + mg.n_units > a.caps.munits) atomicOr(&a.ctr->error, ERR_MUNITS);
-        mg.b0_buf = (uint8_t)ctgt;
-        mg.hv_buf = (uint8_t)dst;
-        mg.out_buf = (uint8_t)t.tgt;
-        mg.g = t.gamma;
-        if (HV && dst == t.tgt && zsize > c0) {
-          // heavy values would be overwritten by the gather: copy them to src first
-          for (uint32_t p = c0; p < zsize; p += COPY_PIECE) {
-            const uint32_t k = atomicAdd(&a.ctr->spills, 1u);
-            if (k >= a.caps.spills) {
-              atomicOr(&a.ctr->error, ERR_SPILL);
-              break;
-            }
-            Leaf l;
-            l.off = t.off + s0 + p;
-            l.size = min(COPY_PIECE, zsize - p);
-            l.bits = 0;
-            l.from = (uint8_t)dst;
-            l.to = (uint8_t)t.src;
-            l.pad = 0;
-            a.spills[k] = l;
-          }
-          mg.hv_buf = (uint8_t)t.src;
-          atomicAdd(&a.ctr->st_copy_records, (unsigned long long)(zsize - c0));
-        }
-        a.merges[i] = mg;
-        heavy_recs += zsize - c0;
-        atomicAdd(&a.ctr->st_merge_records, (unsigned long long)zsize);
+      const uint32_t zsize = zend - s0;
+      Merge& g = mg[k];
+      g.zone_off = t.off + s0;
+      g.tab_off = t.tab_off;
+      g.b0 = c0;
+      g.m = m;
+      g.hbase = lid - z;
+      g.bstart = lid;
+      g.zone_rel = s0;
+      g.n_units = (zsize + MERGE_TILE - 1) / MERGE_TILE;
+      g.b0_buf = (uint8_t)ctgt;
+      g.hv_buf = (uint8_t)dst;
+      g.out_buf = (uint8_t)t.tgt;
+      g.g = t.gamma;
+      spieces[k] = 0;
+      if (HV && dst == t.tgt && zsize > c0) {
+        // heavy values would be overwritten by the gather: copy them to src first
+        spieces[k] = (zsize - c0 + COPY_PIECE - 1) / COPY_PIECE;
+        g.hv_buf = (uint8_t)t.src;
+        sslot[k] = reserve_local(&r, KD_SPILL, spieces[k]);
+        atomicAdd(&r.st_copy, (unsigned long long)(zsize - c0));
       }
+      mslot[k] = reserve_local(&r, KD_MERGE, 1);
+      uslot[k] = reserve_local(&r, KD_MUNIT, g.n_units);
+      atomicAdd(&r.st_heavy, (unsigned long long)(zsize - c0));
+      atomicAdd(&r.st_merge, (unsigned long long)zsize);
     }
     int chi = t.shift;
     if (learned) {
@@ -193,18 +297,56 @@ __global__ __launch_bounds__(256) void k_children(LevelArgs a) {
       const uint64_t d = lo ^ hi_incl;
       chi = (lo > hi_incl) ? 0 : (d ? 64 - __builtin_clzll(d) : 0);
     }
-    emit_child<K, V>(a, t.off + s0, c0, chi, dst, ctgt, false, t.n_root, t.level + 1);
+    ch[k] = plan_child(a, &r, t.off + s0, c0, chi, dst, ctgt, false);
   }
+  ch[ZPT].kind = -1;
   if (threadIdx.x == 0) {
     const uint32_t ob = t.n_buckets - 1u;
     const uint32_t c = st[ob + 1] - st[ob];
-    if (c) atomicAdd(&a.ctr->st_overflow_records, (unsigned long long)c);
-    emit_child<K, V>(a, t.off + st[ob], c, t.hi, dst, t.tgt, true, t.n_root, t.level + 1);
+    if (c) atomicAdd(&r.st_over, (unsigned long long)c);
+    ch[ZPT] = plan_child(a, &r, t.off + st[ob], c, t.hi, dst, t.tgt, true);
+  }
+  __syncthreads();
+  reserve_global(a, &r);
+  if (threadIdx.x == 2 * WAVE) {
     atomicAdd(&a.ctr->st_heavy_keys, (unsigned long long)t.n_heavy);
     atomicAdd(&a.ctr->st_tasks, 1ull);
     atomicAdd(&a.ctr->st_distributed, (unsigned long long)t.size);
   }
-  if (heavy_recs) atomicAdd(&a.ctr->st_heavy_records, heavy_recs);
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k <= ZPT; ++k)
+    if (ch[k].kind >= 0) write_child(a, ch[k], r.base[ch[k].kind], t.n_root, t.level + 1, a.g_override);
+#pragma unroll
+  for (int k = 0; k < ZPT; ++k) {
+    if (mslot[k] == 0xFFFFFFFFu) continue;
+    Merge g = mg[k];
+    const uint32_t mi = r.base[KD_MERGE] + mslot[k];
+    g.unit_base = r.base[KD_MUNIT] + uslot[k];
+    if (mi >= a.caps.merges || g.unit_base + g.n_units > a.caps.munits) {
+      atomicOr(&a.ctr->error, ERR_MERGE);
+      continue;
+    }
+    if (spieces[k]) {
+      const uint32_t si = r.base[KD_SPILL] + sslot[k];
+      const uint32_t zsize = g.n_units ? st[g.bstart + g.m + 1] - st[g.bstart] : 0;
+      for (uint32_t p = g.b0, q = 0; p < zsize; p += COPY_PIECE, ++q) {
+        if (si + q >= a.caps.spills) {
+          atomicOr(&a.ctr->error, ERR_SPILL);
+          break;
+        }
+        Leaf l;
+        l.off = g.zone_off + p;
+        l.size = min(COPY_PIECE, zsize - p);
+        l.bits = 0;
+        l.from = (uint8_t)dst;
+        l.to = (uint8_t)t.src;
+        l.pad = 0;
+        a.spills[si + q] = l;
+      }
+    }
+    a.merges[mi] = g;
+  }
 }
 
 template <typename K, typename V>

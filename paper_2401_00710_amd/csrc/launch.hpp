@@ -12,11 +12,11 @@ struct LevelArgs {
   uint2* units;          // (task index, chunk index) per distribution unit
   uint8_t* tab;          // table arena of this level
   uint32_t slot_bytes;   // bytes per task slot
-  uint32_t pad0;
+  uint32_t cols;         // count-matrix columns per chunk (1, or one per wave for the direct scatter)
   uint32_t* cm;          // count matrices of this level
   // children planning outputs
   Task* next;
-  Leaf* leaf[3];
+  Leaf* leaf[4];
   Leaf* copies;
   Merge* merges;
   Leaf* spills;
@@ -26,7 +26,7 @@ struct LevelArgs {
   uint64_t seed;
   int g_override;
   uint32_t cutoff;
-  uint32_t leaf_max[3];  // size limit of each leaf class
+  uint32_t leaf_max[4];  // size limit of each leaf class
   int plain;
   int key_bits;
 };
@@ -34,8 +34,13 @@ struct LevelArgs {
 template <typename K>
 void launch_plan(const LevelArgs& a, const K* k0, const K* k1, hipStream_t s);
 
+// phase 0: histogram; 1: column and bucket scans; 2: scatter; -1: all three
 template <typename K, typename V>
-void launch_distribute(const LevelArgs& a, Bufs<K, V> b, int g_level_max, uint32_t max_chunks, hipStream_t s);
+void launch_distribute(const LevelArgs& a, Bufs<K, V> b, int g_level_max, uint32_t max_chunks, hipStream_t s,
+                       int phase = -1);
+
+// Count-matrix columns per chunk the distribution of a level will use.
+uint32_t dist_cols(int g_level_max);
 
 void launch_prep(const LevelArgs& a, hipStream_t s);
 
@@ -58,6 +63,26 @@ template <typename K, typename V>
 void launch_merge(const Merge* m, uint32_t n_merges, const uint2* munits, uint32_t n_munits, uint8_t* tab,
                   Bufs<K, V> b, hipStream_t s);
 
+// Learned partitioner (k_mlp.hip).
+int mlp_loss_grad(const float* p, const float* x, const float* y, uint32_t n, float* grad, float* loss, float* part,
+                  hipStream_t s);
+void mlp_forward(const float* p, const float* x, uint32_t n, float* pred, hipStream_t s);
+void mlp_train(const float* x, const float* y, uint32_t n, uint64_t seed, int steps, uint32_t batch, float lr,
+               float* p, float* m, float* v, float* part, float* losses, hipStream_t s);
+template <typename K>
+void mlp_data(const K* sk, uint32_t n, int kb, float* x, float* y, hipStream_t s);
+template <typename K>
+void learned_kernels_draw(const K* keys, uint64_t n, uint64_t seed, uint32_t tag, uint32_t count, K* out,
+                          hipStream_t s);
+template <typename K>
+void learned_kernels_split(const K* sk, const float* pred, uint32_t n, uint32_t zones, float* mono, uint64_t* spl,
+                           hipStream_t s);
+template <typename K>
+void learned_kernels_judge(Task* task, uint8_t* tab, const K* held, uint32_t nh, const uint64_t* spl, void* info,
+                           const float* losses, int steps, hipStream_t s);
+constexpr int MLP_PARAMS = 4353;
+constexpr int MLP_GT = 128;
+
 // Tile sizes of the distribution kernels (records per tile) by key width.
 template <typename K, typename V>
 constexpr uint32_t dist_tile() {
@@ -65,9 +90,11 @@ constexpr uint32_t dist_tile() {
 }
 
 // Leaf classes: the largest size each class sorts, by record layout.
+constexpr int LEAF_CLASSES = 4;
 template <typename K, typename V>
 constexpr uint32_t leaf_cap(int cls) {
-  return cls == 0 ? 2048u : (cls == 1 ? 8192u : ((sizeof(K) == 8 && HasVal<V>::value) ? 8192u : 16384u));
+  return cls == 0 ? 1024u
+                  : (cls == 1 ? 4096u : (cls == 2 ? 8192u : ((sizeof(K) == 8 && HasVal<V>::value) ? 8192u : 16384u)));
 }
 
 }  // namespace dts

@@ -57,8 +57,9 @@ int plan_and_distribute(const K* keys, const V* vals, size_t n, int hi, int skip
   a.n_tasks = 1;
   a.chunk = (uint32_t)chunk;
   a.slot_bytes = sl.bytes;
+  a.cols = dist_cols(g);
   a.caps.units = (uint32_t)units;
-  a.caps.cm = units * nb_cap(g);
+  a.caps.cm = units * a.cols * nb_cap(g);
   a.caps.tab = sl.bytes;
   a.tasks = (Task*)tmp.get(sizeof(Task));
   a.units = (uint2*)tmp.get(sizeof(uint2) * units);
@@ -124,10 +125,10 @@ int leaf_step(const K* keys, const V* vals, const uint64_t* seg, size_t n_seg, i
   std::vector<uint64_t> off(n_seg + 1);
   SCHK(hipMemcpyAsync(off.data(), seg, 8 * (n_seg + 1), hipMemcpyDeviceToHost, s));
   SCHK(hipStreamSynchronize(s));
-  std::vector<Leaf> cls[3];
+  std::vector<Leaf> cls[LEAF_CLASSES];
   for (size_t i = 0; i < n_seg; ++i) {
     const uint64_t b = off[i], e = off[i + 1];
-    if (e < b || e - b > leaf_cap<K, V>(2)) return DTSORT_EINVAL;
+    if (e < b || e - b > leaf_cap<K, V>(LEAF_CLASSES - 1)) return DTSORT_EINVAL;
     if (e == b) continue;
     Leaf l;
     l.off = b;
@@ -136,7 +137,9 @@ int leaf_step(const K* keys, const V* vals, const uint64_t* seg, size_t n_seg, i
     l.from = 0;
     l.to = 1;
     l.pad = 0;
-    const int c = l.size <= leaf_cap<K, V>(0) ? 0 : (l.size <= leaf_cap<K, V>(1) ? 1 : 2);
+    int c = LEAF_CLASSES - 1;
+    for (int k = LEAF_CLASSES - 2; k >= 0; --k)
+      if (l.size <= leaf_cap<K, V>(k)) c = k;
     cls[c].push_back(l);
   }
   Tmp tmp;
@@ -147,7 +150,7 @@ int leaf_step(const K* keys, const V* vals, const uint64_t* seg, size_t n_seg, i
     b.v[0] = const_cast<V*>(vals);
     b.v[1] = out_v;
   }
-  for (int c = 0; c < 3; ++c) {
+  for (int c = 0; c < LEAF_CLASSES; ++c) {
     if (cls[c].empty()) continue;
     Leaf* d = (Leaf*)tmp.get(sizeof(Leaf) * cls[c].size());
     if (!d) return DTSORT_ENOMEM;

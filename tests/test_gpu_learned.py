@@ -1,0 +1,122 @@
+"""Learned partitioner (not part of the paper): FP32 kernels against the
+float64 oracle, and the property that the sort's output is bit-exact
+whatever the model predicts (the model only moves zone boundaries; the
+sampling detector stays the fallback and the judge)."""
+import ctypes as C
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2401_00710_amd as dt
+import workloads as W
+from oracle import mlp
+from oracle import sort as S
+from tests._dev import dev_u64, host_u64, require_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _lib():
+    import paper_2401_00710_amd._lib as L
+    return L.load()
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def test_forward_and_gradient_match_float64_oracle():
+    require_gpu()
+    lib = _lib()
+    rs = np.random.default_rng(0)
+    for trial in range(3):
+        say(f"mlp grad trial={trial}")
+        p = mlp.init_params(trial) + 0.05 * rs.standard_normal(mlp.N_PARAMS)
+        p32 = p.astype(np.float32)
+        x = np.sort(rs.random(3000)).astype(np.float32)
+        y = ((np.arange(3000) + 0.5) / 3000).astype(np.float32)
+        dp = torch.from_numpy(p32).cuda()
+        dx = torch.from_numpy(x).cuda()
+        dy = torch.from_numpy(y).cuda()
+        g = torch.empty(mlp.N_PARAMS, dtype=torch.float32, device="cuda")
+        loss = torch.empty(1, dtype=torch.float32, device="cuda")
+        pred = torch.empty(3000, dtype=torch.float32, device="cuda")
+        assert lib.dtsort_mlp_loss_grad(dp.data_ptr(), dx.data_ptr(), dy.data_ptr(), 3000, g.data_ptr(),
+                                        loss.data_ptr(), _stream()) == 0
+        assert lib.dtsort_mlp_forward(dp.data_ptr(), dx.data_ptr(), 3000, pred.data_ptr(), _stream()) == 0
+        el, eg = mlp.loss_and_grad(p32.astype(np.float64), x.astype(np.float64), y.astype(np.float64))
+        ey, _ = mlp.forward(p32.astype(np.float64), x.astype(np.float64))
+        gg = g.cpu().numpy().astype(np.float64)
+        # float32 accumulation over 3000 samples: relative 1e-4 of the gradient's scale
+        scale = np.abs(eg).max()
+        assert np.max(np.abs(gg - eg)) <= 1e-4 * scale, np.max(np.abs(gg - eg)) / scale
+        assert abs(float(loss.item()) - el) <= 1e-4 * max(el, 1e-6)
+        assert np.max(np.abs(pred.cpu().numpy() - ey)) <= 1e-5
+
+
+def test_initialisation_matches_oracle_bitwise():
+    require_gpu()
+    lib = _lib()
+    keys = np.sort(np.random.default_rng(1).integers(0, 2 ** 63, 4096, dtype=np.uint64))
+    par = torch.empty(mlp.N_PARAMS, dtype=torch.float32, device="cuda")
+    assert lib.dtsort_mlp_train_u64(dev_u64(keys).data_ptr(), keys.size, 7, 0, 256, C.c_float(1e-3),
+                                    par.data_ptr(), None, _stream()) == 0
+    assert np.array_equal(par.cpu().numpy(), mlp.init_params(7).astype(np.float32))
+
+
+def test_training_trajectory_close_to_oracle():
+    """Parity of the trajectory is unpinned beyond tolerance (FP32 vs FP64)."""
+    require_gpu()
+    lib = _lib()
+    k = W.mixture_u64(1 << 14, seed=3).numpy().view(np.uint64)
+    keys = np.sort(k)
+    steps, batch, lr = 60, 256, 3e-3
+    par = torch.empty(mlp.N_PARAMS, dtype=torch.float32, device="cuda")
+    losses = torch.empty(steps, dtype=torch.float32, device="cuda")
+    assert lib.dtsort_mlp_train_u64(dev_u64(keys).data_ptr(), keys.size, 0, steps, batch, C.c_float(lr),
+                                    par.data_ptr(), losses.data_ptr(), _stream()) == 0
+    _, ol = mlp.train(keys, 0, steps, batch, lr)
+    gl = losses.cpu().numpy()
+    assert abs(gl[0] - ol[0]) <= 1e-4 * ol[0]
+    assert gl[-1] < 0.5 * gl[0]
+    assert abs(gl[-1] - ol[-1]) <= 0.25 * ol[-1] + 1e-5
+
+
+@pytest.mark.parametrize("garbage", [False, True])
+def test_learned_sort_bit_exact(garbage):
+    require_gpu()
+    say(f"learned sort garbage={garbage}")
+    k = W.mixture_u64(1 << 22, seed=5).numpy().view(np.uint64)
+    d = dev_u64(k)
+    st = dt.Stats()
+    kw = dict(learned_steps=1, learned_lr=50.0) if garbage else {}
+    dt.sort_u64(d, dt.make_opts(mode=dt.MODE_LEARNED, stats=st, digit_bits=8, **kw))
+    torch.cuda.synchronize()
+    assert np.array_equal(host_u64(d), np.sort(k))
+    assert st.learned_balance > 0 and st.sampling_balance > 0
+    if not garbage:
+        # on the mixture the model's zones beat the digit zones (the exponential
+        # component sits in digit zone 0)
+        assert st.learned_used == 1 and st.learned_balance < st.sampling_balance
+
+
+def test_learned_pairs_stable():
+    require_gpu()
+    k = W.mixture_u64(1 << 21, seed=6).numpy().view(np.uint64)
+    v = np.arange(k.size, dtype=np.uint64)
+    dk, dv = dev_u64(k), dev_u64(v)
+    dt.sort_pairs_u64(dk, dv, dt.make_opts(mode=dt.MODE_LEARNED, digit_bits=8))
+    torch.cuda.synchronize()
+    ek, ev = S.stable_sort_pairs(k, v)
+    assert np.array_equal(host_u64(dk), ek) and np.array_equal(host_u64(dv), ev)
+
+
+def test_profile_counters_filled():
+    require_gpu()
+    k = W.uniform_u32(1 << 22, seed=1).to(torch.int32).cuda()
+    st = dt.Stats()
+    dt.sort_u32(k, dt.make_opts(stats=st, profile=1, digit_bits=8))
+    torch.cuda.synchronize()
+    assert st.kernel_launches[3] >= 1 and st.kernel_ms[3] > 0
+    assert st.kernel_bytes[3] == 2 * 4 * st.records_distributed

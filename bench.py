@@ -68,10 +68,14 @@ def roofline_from_stats(st, kind=3):
     gbs = nb / (ms / 1e3) / 1e9
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
+        # counters taken on an older version of the kernel source do not count
         try:
+            import hashlib
             tr = json.load(open(TRAFFIC_FILE))
-            traffic = tr.get("k_scatter_bytes_per_launch")
-        except (OSError, ValueError):
+            src = os.path.join(ROOT, tr["kernel_source"])
+            if hashlib.sha256(open(src, "rb").read()).hexdigest() == tr["kernel_source_sha256"]:
+                traffic = tr.get("k_scatter_bytes_per_launch")
+        except (OSError, ValueError, KeyError):
             traffic = None
     return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic,

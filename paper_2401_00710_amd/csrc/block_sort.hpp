@@ -32,19 +32,24 @@ constexpr int bsort_match_words() {
   return (THREADS / WAVE) * 256;
 }
 
-// Sorts k[] (and carries ix[] when IDX) by key bits [lo_bit, hi_bit).
-// sk: LDS array of THREADS*ITEMS keys; si: LDS array of THREADS*ITEMS u16
-// (only when IDX); cnt: bsort_cnt_words<THREADS>() u32.  On return k[]/ix[]
-// hold the sorted sequence in the striped layout and sk (si) holds it in order.
-// RANK_LDS needs `mk` (bsort_match_words<THREADS>() zeroed u64 in LDS).
+// Sorts the first n of the THREADS*ITEMS keys held in k[] (and carries ix[]
+// when IDX) by key bits [lo_bit, hi_bit); elements at index >= n are ignored
+// (item rows wholly beyond n are skipped).  sk: LDS array of THREADS*ITEMS
+// keys; si: LDS array of THREADS*ITEMS u16 (only when IDX); cnt:
+// bsort_cnt_words<THREADS>() u32.  RANK_LDS needs `mk`
+// (bsort_match_words<THREADS>() zeroed u64).  On return k[]/ix[] hold the
+// sorted sequence in the striped layout and sk (si) holds it in order.
 template <typename K, int THREADS, int ITEMS, bool IDX, int RANK = RANK_BALLOT>
 __device__ void block_radix_sort(K (&k)[ITEMS], uint16_t (&ix)[ITEMS], int lo_bit, int hi_bit, K* sk,
-                                 uint16_t* si, uint32_t* cnt, unsigned long long* mk = nullptr) {
+                                 uint16_t* si, uint32_t* cnt, unsigned long long* mk = nullptr,
+                                 int n = THREADS * ITEMS) {
   constexpr int WAVES = THREADS / WAVE;
-  static_assert(THREADS >= 256, "one thread per digit in the scan");
+  constexpr int DPT = (256 + THREADS - 1) / THREADS;  // digits per thread in the scan
   const int wv = threadIdx.x / WAVE;
+  const int lane = threadIdx.x & (WAVE - 1);
   uint32_t* tmp = cnt + WAVES * 256;
-  unsigned long long* wm = mk + (RANK == RANK_LDS ? wv * 256 : 0);
+  unsigned long long* wm = mk + (RANK != RANK_BALLOT ? wv * 256 : 0);
+  const int row0 = wv * WAVE * ITEMS;  // first element of this wave
   for (int bit = lo_bit; bit < hi_bit; bit += 8) {
     const int nbits = min(8, hi_bit - bit);
     const uint32_t dmask = (1u << nbits) - 1u;
@@ -52,51 +57,85 @@ __device__ void block_radix_sort(K (&k)[ITEMS], uint16_t (&ix)[ITEMS], int lo_bi
     __syncthreads();
     uint32_t* wc = cnt + wv * 256;
     uint32_t pos[ITEMS];
+    if constexpr (RANK == RANK_PIPE) {
+      uint32_t dg[ITEMS];
+      bool vl[ITEMS];
 #pragma unroll
-    for (int i = 0; i < ITEMS; ++i) {
+      for (int i = 0; i < ITEMS; ++i) {
+        vl[i] = row0 + i * WAVE + lane < n;
+        dg[i] = (uint32_t)(shr<K>(k[i], bit)) & dmask;
+      }
+      rank_pipelined<ITEMS>(dg, vl, wm, wc, pos);
+    }
+#pragma unroll
+    for (int i = 0; i < (RANK == RANK_PIPE ? 0 : ITEMS); ++i) {
+      pos[i] = 0;
+      if (row0 + i * WAVE >= n) continue;  // whole row is padding (uniform per wave)
+      const bool valid = row0 + i * WAVE + lane < n;
       const uint32_t d = (uint32_t)(shr<K>(k[i], bit)) & dmask;
       uint64_t peers;
       if constexpr (RANK == RANK_LDS) {
-        peers = lds_match(wm, d, true);
+        peers = lds_match(wm, d, valid);
+      } else if constexpr (RANK == RANK_HYBRID) {
+        peers = hybrid_match(wm, d, nbits, valid);
       } else {
-        peers = match_peers(d, nbits, true);
+        peers = match_peers(d, nbits, valid);
       }
       const uint32_t r = mbcnt(peers);
       const uint32_t c = (uint32_t)__popcll(peers);
-      const uint32_t base = wc[d];
-      pos[i] = base + r;
-      if (r == 0) wc[d] = base + c;
+      if (valid) {
+        const uint32_t base = wc[d];
+        pos[i] = base + r;
+        if (r == 0) wc[d] = base + c;
+      }
     }
     __syncthreads();
-    // exclusive offsets in (digit, wave) order
-    const int t = threadIdx.x;
-    uint32_t s = 0;
-    if (t < 256) {
-      for (int w = 0; w < WAVES; ++w) s += cnt[w * 256 + t];
+    // exclusive offsets in (digit, wave) order; thread t owns digits [t*DPT, t*DPT+DPT)
+    uint32_t sd[DPT];
+    uint32_t S = 0;
+#pragma unroll
+    for (int j = 0; j < DPT; ++j) {
+      const int d = threadIdx.x * DPT + j;
+      uint32_t x = 0;
+      if (d < 256) {
+        for (int w = 0; w < WAVES; ++w) x += cnt[w * 256 + d];
+      }
+      sd[j] = x;
+      S += x;
     }
     uint32_t total;
-    uint32_t run = block_excl_scan<THREADS>(t < 256 ? s : 0u, tmp, &total);
-    if (t < 256) {
-      for (int w = 0; w < WAVES; ++w) {
-        const uint32_t c = cnt[w * 256 + t];
-        cnt[w * 256 + t] = run;
-        run += c;
+    uint32_t run = block_excl_scan<THREADS>(S, tmp, &total);
+#pragma unroll
+    for (int j = 0; j < DPT; ++j) {
+      const int d = threadIdx.x * DPT + j;
+      if (d < 256) {
+        uint32_t r2 = run;
+        for (int w = 0; w < WAVES; ++w) {
+          const uint32_t c = cnt[w * 256 + d];
+          cnt[w * 256 + d] = r2;
+          r2 += c;
+        }
       }
+      run += sd[j];
     }
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
-      const uint32_t d = (uint32_t)(shr<K>(k[i], bit)) & dmask;
-      const uint32_t p = pos[i] + wc[d];
-      sk[p] = k[i];
-      if constexpr (IDX) si[p] = ix[i];
+      if (row0 + i * WAVE + lane < n) {
+        const uint32_t d = (uint32_t)(shr<K>(k[i], bit)) & dmask;
+        const uint32_t p = pos[i] + wc[d];
+        sk[p] = k[i];
+        if constexpr (IDX) si[p] = ix[i];
+      }
     }
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
       const int e = striped_index<THREADS, ITEMS>(i);
-      k[i] = sk[e];
-      if constexpr (IDX) ix[i] = si[e];
+      if (e < n) {
+        k[i] = sk[e];
+        if constexpr (IDX) ix[i] = si[e];
+      }
     }
     __syncthreads();
   }

@@ -113,7 +113,7 @@ struct LevelCounters {
   uint64_t next_tab;        // their table bytes
   uint32_t next_max_size;   // largest next-level task
   uint32_t next_records;    // records in next-level tasks (saturating)
-  uint32_t leaf[4];         // leaf sorts per size class
+  uint32_t leaf[6];         // leaf sorts per size class
   uint32_t copies;          // copy items
   uint32_t merges;          // merge items
   uint32_t merge_units;     // gather units
@@ -217,18 +217,60 @@ __device__ inline uint64_t match_peers(uint32_t v, int nbits, bool valid) {
 // it (3 LDS operations instead of one ballot per bit).  LDS instructions of
 // one wave execute in issue order, so the read sees every lane's OR and the
 // clear follows every lane's read.  The table must start (and is left) zero.
+//
+// Each 64-bit slot is two 32-bit halves: lanes 0-31 OR into the low half and
+// lanes 32-63 into the high half, so the OR and the clear are 32-bit
+// operations and only the read is 64-bit.
 __device__ inline uint64_t lds_match(unsigned long long* wm, uint32_t v, bool valid) {
-  const unsigned long long bit = 1ull << (threadIdx.x & (WAVE - 1));
+  const uint32_t lane = threadIdx.x & (WAVE - 1);
+  uint32_t* half = reinterpret_cast<uint32_t*>(wm + v) + (lane >> 5);
+  const uint32_t bit = 1u << (lane & 31);
   unsigned long long peers = 0;
   if (valid) {
-    __hip_atomic_fetch_or(wm + v, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __hip_atomic_fetch_or(half, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     peers = __hip_atomic_load(wm + v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    __hip_atomic_store(wm + v, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __hip_atomic_store(half, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   }
   return peers;
 }
 
-enum RankMode { RANK_BALLOT = 0, RANK_LDS = 1 };
+enum RankMode { RANK_BALLOT = 0, RANK_LDS = 1, RANK_HYBRID = 2, RANK_PIPE = 3 };
+
+// Hybrid: ballots match the low 4 bits, the LDS table matches the remaining
+// high bits (a table of at most 2^(nbits-4) slots, small enough that distinct
+// slots sit in distinct banks); the peers are the intersection.
+__device__ inline uint64_t hybrid_match(unsigned long long* wm, uint32_t v, int nbits, bool valid) {
+  const int lo = nbits < 4 ? nbits : 4;
+  uint64_t peers = match_peers(v & ((1u << lo) - 1u), lo, valid);
+  if (nbits > lo) peers &= lds_match(wm, v >> lo, valid);
+  return peers;
+}
+
+// Stable ranking of ITEMS items per lane against per-wave running counters
+// `crow` (one per value), pipelined: all items' LDS matches are issued back
+// to back, then every value's leader lane (lowest lane holding it) takes the
+// running count with one atomic add-and-return, and its peers fetch that
+// base from the leader lane.  pos[i] = running count before item i + rank
+// among this item's peers.  LDS operations of a wave run in issue order, so
+// the counts advance item by item exactly as in a sequential loop.
+template <int ITEMS>
+__device__ inline void rank_pipelined(const uint32_t (&v)[ITEMS], const bool (&valid)[ITEMS], unsigned long long* wm,
+                                      uint32_t* crow, uint32_t (&pos)[ITEMS]) {
+  uint64_t pe[ITEMS];
+#pragma unroll
+  for (int i = 0; i < ITEMS; ++i) pe[i] = lds_match(wm, v[i], valid[i]);
+  uint32_t old[ITEMS], ldr[ITEMS], rk[ITEMS];
+  const uint32_t lane = threadIdx.x & (WAVE - 1);
+#pragma unroll
+  for (int i = 0; i < ITEMS; ++i) {
+    rk[i] = mbcnt(pe[i]);
+    ldr[i] = valid[i] ? (uint32_t)__builtin_ctzll(pe[i]) : lane;
+    old[i] = 0;
+    if (valid[i] && rk[i] == 0) old[i] = atomicAdd(&crow[v[i]], (uint32_t)__popcll(pe[i]));
+  }
+#pragma unroll
+  for (int i = 0; i < ITEMS; ++i) pos[i] = (uint32_t)__shfl((int)old[i], (int)ldr[i], WAVE) + rk[i];
+}
 
 // Exclusive scan of one value per thread across the workgroup.  `tmp` holds
 // THREADS/64 + 1 words of LDS.  Returns the exclusive prefix; *total gets the sum.

@@ -84,7 +84,10 @@ void launch_prep(const LevelArgs& a, hipStream_t s) {
 static int rank_mode() {
   static int m = [] {
     const char* e = getenv("DTSORT_RANK");
-    return (e && e[0] == 'b') ? (int)RANK_BALLOT : (int)RANK_LDS;
+    if (e && e[0] == 'b') return (int)RANK_BALLOT;
+    if (e && e[0] == 'h') return (int)RANK_HYBRID;
+    if (e && e[0] == 'p') return (int)RANK_PIPE;
+    return (int)RANK_LDS;
   }();
   return m;
 }
@@ -261,7 +264,7 @@ __global__ __launch_bounds__(T) void k_scatter(LevelArgs a, Bufs<K, V> bf) {
   constexpr bool HV = HasVal<V>::value;
   static_assert(!HV || sizeof(V) <= sizeof(K), "values are staged in the key buffer");
   __shared__ uint32_t cnt[WAVES * NBMAX];
-  __shared__ unsigned long long mk[RANK == RANK_LDS ? WAVES * NBMAX : 1];
+  __shared__ unsigned long long mk[RANK == RANK_BALLOT ? 1 : WAVES * NBMAX];  // zeroed match tables
   __shared__ uint32_t run_off[NBMAX];
   __shared__ int32_t gdelta[NBMAX];
   __shared__ uint32_t L[(1 << GMAX) + 1];
@@ -281,7 +284,7 @@ __global__ __launch_bounds__(T) void k_scatter(LevelArgs a, Bufs<K, V> bf) {
   const uint32_t nb = t.n_buckets;
   for (uint32_t b = threadIdx.x; b < nb; b += T)
     run_off[b] = starts[b] + a.cm[t.cm_off + (uint64_t)b * t.n_chunks * a.cols + u.y];
-  if constexpr (RANK == RANK_LDS) {
+  if constexpr (RANK != RANK_BALLOT) {
     for (int i = threadIdx.x; i < WAVES * NBMAX; i += T) mk[i] = 0ull;
   }
   __syncthreads();
@@ -292,7 +295,7 @@ __global__ __launch_bounds__(T) void k_scatter(LevelArgs a, Bufs<K, V> bf) {
   const int nbits = nb > 1 ? 32 - __builtin_clz(nb - 1) : 1;
   const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
   uint32_t* crow = cnt + wv * NBMAX;
-  unsigned long long* wm = mk + (RANK == RANK_LDS ? wv * NBMAX : 0);
+  unsigned long long* wm = mk + (RANK != RANK_BALLOT ? wv * NBMAX : 0);
   const uint32_t beg = u.y * a.chunk;
   const uint32_t end = min(t.size, beg + a.chunk);
 
@@ -318,8 +321,17 @@ __global__ __launch_bounds__(T) void k_scatter(LevelArgs a, Bufs<K, V> bf) {
     for (uint32_t j = lane; j < nb; j += WAVE) crow[j] = 0;
     uint32_t bk[ITEMS];
     uint32_t pos[ITEMS];
+    if constexpr (RANK == RANK_PIPE) {
+      bool vl[ITEMS];
 #pragma unroll
-    for (int i = 0; i < ITEMS; ++i) {
+      for (int i = 0; i < ITEMS; ++i) {
+        vl[i] = (uint32_t)striped_index<T, ITEMS>(i) < tile_n;
+        bk[i] = vl[i] ? bucket_of<K>(kk[i], pr, L, H, SPL) : 0u;
+      }
+      rank_pipelined<ITEMS>(bk, vl, wm, crow, pos);
+    }
+#pragma unroll
+    for (int i = 0; i < (RANK == RANK_PIPE ? 0 : ITEMS); ++i) {
       const uint32_t e = (uint32_t)striped_index<T, ITEMS>(i);
       const bool valid = e < tile_n;
       const uint32_t b = valid ? bucket_of<K>(kk[i], pr, L, H, SPL) : 0u;
@@ -327,6 +339,8 @@ __global__ __launch_bounds__(T) void k_scatter(LevelArgs a, Bufs<K, V> bf) {
       uint64_t peers;
       if constexpr (RANK == RANK_LDS) {
         peers = lds_match(wm, b, valid);
+      } else if constexpr (RANK == RANK_HYBRID) {
+        peers = hybrid_match(wm, b, nbits, valid);
       } else {
         peers = match_peers(b, nbits, valid);
       }
@@ -388,9 +402,13 @@ __global__ __launch_bounds__(T) void k_scatter(LevelArgs a, Bufs<K, V> bf) {
       }
     }
     __syncthreads();
-    for (uint32_t j = threadIdx.x; j < tile_n; j += T) {
-      const uint32_t gp = (uint32_t)(gdelta[stage_b[j]] + (int32_t)j);
-      if (gp < t.size) kout[gp] = stage[j];
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) {
+      const uint32_t j = threadIdx.x + it * T;
+      if (j < tile_n) {
+        const uint32_t gp = (uint32_t)(gdelta[stage_b[j]] + (int32_t)j);
+        if (gp < t.size) kout[gp] = stage[j];
+      }
     }
     if constexpr (HV) {
       const V* vin = bf.v[t.src] + t.off;
@@ -508,10 +526,10 @@ __global__ __launch_bounds__(T) void k_scatter_direct(LevelArgs a, Bufs<K, V> bf
   }
 }
 
-template <typename K, typename V, int NBMAX, int T, int RANK, bool DIRECT>
+template <typename K, typename V, int NBMAX, int T, int RANK, bool DIRECT, int SITEMS_REQ = 0>
 static void launch_dist_variant(const LevelArgs& a, Bufs<K, V> b, uint32_t max_chunks, hipStream_t s, int phase) {
   constexpr int HITEMS = sizeof(K) == 4 ? 16 : 8;
-  constexpr int SITEMS = sizeof(K) == 4 ? 16 : 8;
+  constexpr int SITEMS = SITEMS_REQ ? SITEMS_REQ : (sizeof(K) == 4 ? 16 : 8);
   const uint32_t nu = a.caps.units;  // bound on the units; k_prep stores the exact count
   if (phase < 0 || phase == 0)
     hipLaunchKernelGGL((k_hist<K, T, HITEMS, NBMAX, DIRECT>), dim3(nu), dim3(T), 0, s, a, (const K*)b.k[0],
@@ -531,6 +549,17 @@ static void launch_dist_variant(const LevelArgs& a, Bufs<K, V> b, uint32_t max_c
       hipLaunchKernelGGL((k_scatter<K, V, T, SITEMS, NBMAX, RANK>), dim3(nu), dim3(T), 0, s, a, b);
     }
   }
+}
+
+// Tile shape of the staged scatter for digit widths <= 8 (tuning knob
+// DTSORT_SCATTER_CFG): 0 = 512 threads x 16 keys (x 8 for 64-bit keys),
+// 1 = 256 x 16, 2 = 512 x 8, 3 = 256 x 32.
+static int scatter_cfg() {
+  static int m = [] {
+    const char* e = getenv("DTSORT_SCATTER_CFG");
+    return e ? atoi(e) : 0;
+  }();
+  return m;
 }
 
 // Scatter variant (tuning knob: DTSORT_SCATTER=staged|direct).
@@ -558,13 +587,28 @@ void launch_distribute(const LevelArgs& a, Bufs<K, V> b, int g_level_max, uint32
     return;
   }
   if (g_level_max <= 8) {
+    const int cfg = scatter_cfg();
     if (rank_mode() == RANK_BALLOT)
       launch_dist_variant<K, V, 512, 512, RANK_BALLOT, false>(a, b, max_chunks, s, phase);
+    else if (rank_mode() == RANK_HYBRID)
+      launch_dist_variant<K, V, 512, 512, RANK_HYBRID, false>(a, b, max_chunks, s, phase);
+    else if (rank_mode() == RANK_PIPE && cfg == 0)
+      launch_dist_variant<K, V, 512, 512, RANK_PIPE, false>(a, b, max_chunks, s, phase);
+    else if (rank_mode() == RANK_PIPE)
+      launch_dist_variant<K, V, 512, 256, RANK_PIPE, false>(a, b, max_chunks, s, phase);
+    else if (cfg == 1)
+      launch_dist_variant<K, V, 512, 256, RANK_LDS, false>(a, b, max_chunks, s, phase);
+    else if (cfg == 2)
+      launch_dist_variant<K, V, 512, 512, RANK_LDS, false, sizeof(K) == 4 ? 8 : 4>(a, b, max_chunks, s, phase);
+    else if (cfg == 3)
+      launch_dist_variant<K, V, 512, 256, RANK_LDS, false, sizeof(K) == 4 ? 32 : 16>(a, b, max_chunks, s, phase);
     else
       launch_dist_variant<K, V, 512, 512, RANK_LDS, false>(a, b, max_chunks, s, phase);
   } else {
     if (rank_mode() == RANK_BALLOT)
       launch_dist_variant<K, V, 2048, 256, RANK_BALLOT, false>(a, b, max_chunks, s, phase);
+    else if (rank_mode() == RANK_PIPE)
+      launch_dist_variant<K, V, 2048, 256, RANK_PIPE, false>(a, b, max_chunks, s, phase);
     else
       launch_dist_variant<K, V, 2048, 256, RANK_LDS, false>(a, b, max_chunks, s, phase);
   }

@@ -1,6 +1,8 @@
 // Step 1 of Alg. 2 (Section 3.1; the sampled key range and overflow bucket of
 // Section 5), one workgroup per subproblem, and the base case of Section 3.5
 // (a stable sort in LDS), one workgroup per small subproblem.
+#include <cstdlib>
+
 #include "block_sort.hpp"
 #include "launch.hpp"
 
@@ -67,7 +69,8 @@ __global__ __launch_bounds__(1024) void k_plan(LevelArgs a, const K* k0, const K
     block_or_and<K, T, ITEMS>(kk, (int)ns, red, &vor, &vand);
     const K diff = (vor ^ vand) & mask_below<K>(hi);
     if (diff) {
-      block_radix_sort<K, T, ITEMS, false>(kk, dummy, trailing_zeros(diff), bit_length(diff), sk, nullptr, cnt);
+      block_radix_sort<K, T, ITEMS, false>(kk, dummy, trailing_zeros(diff), bit_length(diff), sk, nullptr, cnt,
+                                           nullptr, (int)ns);
     } else {
 #pragma unroll
       for (int i = 0; i < ITEMS; ++i) sk[striped_index<T, ITEMS>(i)] = kk[i];
@@ -137,17 +140,17 @@ void launch_plan(const LevelArgs& a, const K* k0, const K* k1, hipStream_t s) {
 // ---------------------------------------------------------------- leaves
 // Base case: a stable radix sort in LDS of a subproblem of at most T*ITEMS
 // records, only over the bit range in which its keys differ.
-template <typename K, typename V, int T, int ITEMS>
+template <typename K, typename V, int T, int ITEMS, int RANKREQ>
 __global__ __launch_bounds__(T) void k_leaf(const Leaf* items, Bufs<K, V> bf) {
   constexpr int N = T * ITEMS;
   constexpr bool HV = HasVal<V>::value;
   __shared__ K sk[N];
   __shared__ uint16_t si[HV ? N : 1];
   __shared__ uint32_t cnt[bsort_cnt_words<T>()];
-  // LDS-match ranking when its tables fit next to the keys, else ballot ranking
-  constexpr bool USE_LDS = N * sizeof(K) + (HV ? N * 2 : 0) + 4 * bsort_cnt_words<T>() +
-                               8 * bsort_match_words<T>() <= 150 * 1024;
-  constexpr int RANK = USE_LDS ? RANK_LDS : RANK_BALLOT;
+  // LDS-match ranking (if requested and its tables fit next to the keys), else ballot ranking
+  constexpr bool USE_LDS = RANKREQ != RANK_BALLOT && N * sizeof(K) + (HV ? N * 2 : 0) + 4 * bsort_cnt_words<T>() +
+                                                         8 * bsort_match_words<T>() <= 150 * 1024;
+  constexpr int RANK = USE_LDS ? RANKREQ : RANK_BALLOT;
   __shared__ unsigned long long mk[USE_LDS ? bsort_match_words<T>() : 1];
   __shared__ K red[2 * (T / WAVE)];
   if constexpr (USE_LDS) {
@@ -169,7 +172,7 @@ __global__ __launch_bounds__(T) void k_leaf(const Leaf* items, Bufs<K, V> bf) {
   block_or_and<K, T, ITEMS>(kk, n, red, &vor, &vand);
   const K diff = (vor ^ vand) & mask_below<K>(it.bits);
   if (diff) {
-    block_radix_sort<K, T, ITEMS, HV, RANK>(kk, ix, trailing_zeros(diff), bit_length(diff), sk, si, cnt, mk);
+    block_radix_sort<K, T, ITEMS, HV, RANK>(kk, ix, trailing_zeros(diff), bit_length(diff), sk, si, cnt, mk, n);
   }
 #pragma unroll
   for (int i = 0; i < ITEMS; ++i) {
@@ -195,21 +198,55 @@ __global__ __launch_bounds__(T) void k_leaf(const Leaf* items, Bufs<K, V> bf) {
   }
 }
 
+// Ranking mode of the leaf sorts (tuning knob: DTSORT_LEAF_RANK=ballot|lds).
+static int leaf_rank_mode() {
+  static int m = [] {
+    const char* e = getenv("DTSORT_LEAF_RANK");
+    if (e && e[0] == 'b') return (int)RANK_BALLOT;
+    if (e && e[0] == 'h') return (int)RANK_HYBRID;
+    if (e && e[0] == 'p') return (int)RANK_PIPE;
+    return (int)RANK_LDS;
+  }();
+  return m;
+}
+
+template <typename K, typename V, int RANK>
+static void launch_leaf_r(const Leaf* items, uint32_t n_items, int cls, Bufs<K, V> b, hipStream_t s) {
+  constexpr bool big8 = sizeof(K) == 8 && HasVal<V>::value;
+  switch (cls) {
+    case 0:
+      hipLaunchKernelGGL((k_leaf<K, V, 64, 4, RANK>), dim3(n_items), dim3(64), 0, s, items, b);
+      break;
+    case 1:
+      hipLaunchKernelGGL((k_leaf<K, V, 256, 4, RANK>), dim3(n_items), dim3(256), 0, s, items, b);
+      break;
+    case 2:
+      hipLaunchKernelGGL((k_leaf<K, V, 256, 16, RANK>), dim3(n_items), dim3(256), 0, s, items, b);
+      break;
+    case 3:
+      hipLaunchKernelGGL((k_leaf<K, V, 512, 16, RANK>), dim3(n_items), dim3(512), 0, s, items, b);
+      break;
+    default:
+      if constexpr (big8) {
+        hipLaunchKernelGGL((k_leaf<K, V, 512, 16, RANK>), dim3(n_items), dim3(512), 0, s, items, b);
+      } else {
+        hipLaunchKernelGGL((k_leaf<K, V, 1024, 16, RANK>), dim3(n_items), dim3(1024), 0, s, items, b);
+      }
+  }
+}
+
 template <typename K, typename V>
 void launch_leaf(const Leaf* items, uint32_t n_items, int cls, Bufs<K, V> b, hipStream_t s) {
   if (n_items == 0) return;
-  constexpr bool big8 = sizeof(K) == 8 && HasVal<V>::value;
-  if (cls == 0) {
-    hipLaunchKernelGGL((k_leaf<K, V, 256, 4>), dim3(n_items), dim3(256), 0, s, items, b);
-  } else if (cls == 1) {
-    hipLaunchKernelGGL((k_leaf<K, V, 256, 16>), dim3(n_items), dim3(256), 0, s, items, b);
-  } else if constexpr (big8) {
-    hipLaunchKernelGGL((k_leaf<K, V, 512, 16>), dim3(n_items), dim3(512), 0, s, items, b);
-  } else if (cls == 2) {
-    hipLaunchKernelGGL((k_leaf<K, V, 512, 16>), dim3(n_items), dim3(512), 0, s, items, b);
-  } else {
-    hipLaunchKernelGGL((k_leaf<K, V, 1024, 16>), dim3(n_items), dim3(1024), 0, s, items, b);
-  }
+  const int m = leaf_rank_mode();
+  if (m == RANK_BALLOT)
+    launch_leaf_r<K, V, RANK_BALLOT>(items, n_items, cls, b, s);
+  else if (m == RANK_HYBRID)
+    launch_leaf_r<K, V, RANK_HYBRID>(items, n_items, cls, b, s);
+  else if (m == RANK_PIPE)
+    launch_leaf_r<K, V, RANK_PIPE>(items, n_items, cls, b, s);
+  else
+    launch_leaf_r<K, V, RANK_LDS>(items, n_items, cls, b, s);
 }
 
 template void launch_plan<uint32_t>(const LevelArgs&, const uint32_t*, const uint32_t*, hipStream_t);

@@ -21,7 +21,7 @@ constexpr uint32_t COPY_PIECE = 1u << 20;   // records per copy item
 constexpr uint32_t MERGE_TILE = 4096;       // outputs per gather unit
 
 // Kinds of work a finished distribution hands on (one output list each).
-enum Kind : int { KD_TASK = 0, KD_LEAF0 = 1, KD_COPY = 5, KD_MERGE = 6, KD_MUNIT = 7, KD_SPILL = 8, KD_N = 9 };
+enum Kind : int { KD_TASK = 0, KD_LEAF0 = 1, KD_COPY = 1 + LEAF_CLASSES, KD_MERGE, KD_MUNIT, KD_SPILL, KD_N };
 
 struct Child {
   uint64_t off;

@@ -4,6 +4,8 @@
 
 namespace dts {
 
+constexpr int LEAF_CLASSES_MAX = 6;
+
 // Per-level device state handed to the kernels of one recursion level.
 struct LevelArgs {
   Task* tasks;
@@ -16,7 +18,7 @@ struct LevelArgs {
   uint32_t* cm;          // count matrices of this level
   // children planning outputs
   Task* next;
-  Leaf* leaf[4];
+  Leaf* leaf[LEAF_CLASSES_MAX];
   Leaf* copies;
   Merge* merges;
   Leaf* spills;
@@ -26,7 +28,7 @@ struct LevelArgs {
   uint64_t seed;
   int g_override;
   uint32_t cutoff;
-  uint32_t leaf_max[4];  // size limit of each leaf class
+  uint32_t leaf_max[LEAF_CLASSES_MAX];  // size limit of each leaf class
   int plain;
   int key_bits;
 };
@@ -90,11 +92,13 @@ constexpr uint32_t dist_tile() {
 }
 
 // Leaf classes: the largest size each class sorts, by record layout.
-constexpr int LEAF_CLASSES = 4;
+constexpr int LEAF_CLASSES = 5;
 template <typename K, typename V>
 constexpr uint32_t leaf_cap(int cls) {
-  return cls == 0 ? 1024u
-                  : (cls == 1 ? 4096u : (cls == 2 ? 8192u : ((sizeof(K) == 8 && HasVal<V>::value) ? 8192u : 16384u)));
+  return cls == 0 ? 256u
+                  : (cls == 1 ? 1024u
+                              : (cls == 2 ? 4096u
+                                          : (cls == 3 ? 8192u : ((sizeof(K) == 8 && HasVal<V>::value) ? 8192u : 16384u))));
 }
 
 }  // namespace dts

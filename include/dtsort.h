@@ -96,11 +96,22 @@ typedef struct dtsort_opts {
   int32_t mode;           /* dtsort_mode */
   int32_t digit_bits;     /* 0 = automatic (log2 of the cube root of n', clamped to [8, 10]); else 1..10 */
   int32_t lds_cutoff;     /* 0 = automatic; base-case threshold theta (records) */
-  int32_t tuned;          /* 1 = take digit_bits / lds_cutoff from the autotuner's table when they are 0 */
-  int32_t learned_steps;  /* LEARNED: optimiser steps (0 = default 512) */
+  int32_t tuned;          /* 1 = take digit_bits / lds_cutoff / tile_shape from the tuning table when they are 0
+                             (the file named by DTSORT_TUNE_FILE, else tune_table.txt beside the library;
+                             written by the package's autotuner) */
+  int32_t learned_steps;  /* LEARNED: optimiser steps (0 = default 256) */
   int32_t learned_batch;  /* LEARNED: batch size (0 = default 1024) */
   float learned_lr;       /* LEARNED: Adam step size (0 = default 3e-3) */
   int32_t profile;        /* 1 = time every kernel launch with HIP events into stats (adds syncs) */
+  int32_t tile_shape;     /* scatter tile for digits <= 8 bits: 0 = automatic, 1 = 512 threads x 16 keys
+                             (x 8 for 64-bit keys), 2 = 256 x 16, 3 = 512 x 8, 4 = 256 x 32 */
+  int32_t graph;          /* 1 = device-driven schedule recorded once into a HIP graph and replayed: no
+                             host read-back between levels, the call only enqueues one graph launch.
+                             The graph is cached per (entry point, pointers, sizes, options) with its
+                             own worst-case workspace (at most 4 per device, least recently used
+                             evicted); a first call records and instantiates it.  Not with LEARNED
+                             mode or profile.  Errors (invalid segment offsets) are reported only
+                             when stats is given, which makes the call wait for the graph. */
   void* workspace;        /* optional device buffer for the ping-pong partner (see dtsort_workspace_bytes) */
   size_t workspace_bytes;
   dtsort_stats* stats;    /* optional host pointer */

@@ -60,6 +60,8 @@ class Opts(C.Structure):
         ("learned_batch", C.c_int32),
         ("learned_lr", C.c_float),
         ("profile", C.c_int32),
+        ("tile_shape", C.c_int32),
+        ("graph", C.c_int32),
         ("workspace", C.c_void_p),
         ("workspace_bytes", C.c_size_t),
         ("stats", C.POINTER(Stats)),

@@ -120,6 +120,8 @@ struct LevelCounters {
   uint32_t spills;          // heavy-value spill copies (pairs)
   uint32_t error;           // nonzero = a capacity check failed
   uint32_t cur_units;       // distribution units of this level (set by the prep step)
+  uint32_t cur_tasks;       // tasks of this level (set by the prep step)
+  uint32_t chunk;           // records per distribution unit (set by the prep step)
   // statistics (accumulated)
   unsigned long long st_heavy_keys, st_heavy_records, st_leaf_records, st_copy_records, st_merge_records,
       st_overflow_records, st_tasks, st_distributed;
@@ -319,6 +321,25 @@ __device__ inline uint32_t block_excl_scan_array(uint32_t* arr, int n, uint32_t*
   }
   __syncthreads();
   return total;
+}
+
+// ------------------------------------------------------- buffer loads
+// Raw buffer loads (CDNA buffer instructions) over a resource covering
+// [base, base + bytes): an access past the end returns zero instead of
+// touching memory, so tile loads need no per-element clamp and keep one
+// 32-bit offset per thread.  The fourth descriptor word is the gfx9-family
+// default (no swizzle, 32-bit data format).
+__device__ inline __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+template <typename K>
+__device__ inline K buf_load(__amdgpu_buffer_rsrc_t r, uint32_t off_bytes) {
+  if constexpr (sizeof(K) == 8) {
+    return __builtin_bit_cast(K, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off_bytes, 0, 0));
+  } else {
+    return (K)__builtin_amdgcn_raw_buffer_load_b32(r, (int)off_bytes, 0, 0);
+  }
 }
 
 // ------------------------------------------------------- bucket-id function

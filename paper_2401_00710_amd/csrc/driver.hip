@@ -6,10 +6,12 @@
 // read back one block of counters -> leaf sorts and copies of this level.
 // After the last level the dovetail merges (Step 4) run deepest level first,
 // so every zone merges after its light bucket is completely sorted.
+#include <dlfcn.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -43,21 +45,34 @@ constexpr int MAX_LEVELS = 160;
 struct LevelKeep {
   DevBuf tab, merges, munits, spills;
   uint32_t n_merges = 0, n_munits = 0, n_spills = 0;
+  Caps caps{};
   double merge_records = 0;
 };
 
+// Device buffers of one sort schedule (the eager level loop of a context, or
+// one recorded graph).
+struct Work {
+  DevBuf tk;                      // ping-pong partner of keys (and values), unless the caller gives one
+  DevBuf tasks[2], units, cm, leaf[LEAF_CLASSES], copies, ctr;
+  std::vector<LevelKeep> lv;
+};
+
+struct GraphEntry;
+
 struct Ctx {
   int device = -1;
-  DevBuf tk, tv;                 // ping-pong partner of keys / values
-  DevBuf tasks[2], units, cm, leaf[LEAF_CLASSES], copies, ctr, scratch, lrn;
-  std::vector<LevelKeep> lv;
+  Work w;
+  DevBuf lrn;
   LevelCounters* h_ctr = nullptr;  // pinned
-  void* h_stage = nullptr;         // pinned staging (task upload etc.)
+  void* h_stage = nullptr;         // pinned staging
   hipEvent_t done = nullptr;
   hipStream_t last_stream = nullptr;
   bool has_last = false;
   std::vector<hipEvent_t> ev_pool;
   struct Ctx* inner = nullptr;     // separate state for the sort of the learned partitioner's sample
+  std::vector<GraphEntry*> graphs;
+  hipStream_t cap_stream = nullptr;  // graphs are recorded on this stream
+  uint64_t clock = 0;
 };
 
 // Per-kernel timing with HIP events on the sort's stream (opts->profile).
@@ -146,8 +161,8 @@ static int ensure(DevBuf& b, size_t bytes, hipStream_t s) {
 static Ctx* new_ctx(int dev) {
   Ctx* c = new Ctx();
   c->device = dev;
-  c->lv.resize(MAX_LEVELS);
-  if (hipHostMalloc((void**)&c->h_ctr, sizeof(LevelCounters) * MAX_LEVELS) != hipSuccess ||
+  c->w.lv.resize(MAX_LEVELS);
+  if (hipHostMalloc((void**)&c->h_ctr, sizeof(LevelCounters) * (MAX_LEVELS + 1)) != hipSuccess ||
       hipHostMalloc(&c->h_stage, 1 << 16) != hipSuccess ||
       hipEventCreateWithFlags(&c->done, hipEventDisableTiming) != hipSuccess) {
     (void)hipGetLastError();
@@ -177,6 +192,22 @@ static void free_buf(DevBuf& b) {
   b.cap = 0;
 }
 
+static void free_work(Work& w) {
+  free_buf(w.tk);
+  for (auto& b : w.tasks) free_buf(b);
+  free_buf(w.units);
+  free_buf(w.cm);
+  for (auto& b : w.leaf) free_buf(b);
+  free_buf(w.copies);
+  free_buf(w.ctr);
+  for (auto& l : w.lv) {
+    free_buf(l.tab);
+    free_buf(l.merges);
+    free_buf(l.munits);
+    free_buf(l.spills);
+  }
+}
+
 template <typename K, typename V>
 struct SortJob {
   Bufs<K, V> bufs;
@@ -193,16 +224,82 @@ static uint32_t cutoff_for(int kb, bool hv, int req) {
   return std::min<uint32_t>(cap, std::max<uint32_t>(2u, (uint32_t)req));
 }
 
-// Tuned defaults (autotuner table); SAMPLING mode, indexed by key layout.
-struct Tuned {
-  int digit_bits;
-  int cutoff;
+// ---------------------------------------------------------------- tuning
+// Rows of the tuning table: key bytes, value bytes, segmented (0/1), a range
+// [lo, hi] of floor(log2 n), and the parameters chosen for it (digit bits,
+// base-case cutoff, scatter tile shape; 0 = automatic).  The first matching
+// row wins.
+struct TuneRow {
+  int kb, vb, seg, lo, hi, digit_bits, cutoff, tile;
 };
-static Tuned tuned_params(int kb, bool hv, size_t n) {
-  (void)n;
-  (void)hv;
-  (void)kb;
-  return Tuned{8, 0};
+
+static std::string lib_dir() {
+  Dl_info info;
+  if (dladdr((void*)&dtsort_default_opts, &info) && info.dli_fname) {
+    std::string p(info.dli_fname);
+    const size_t k = p.rfind('/');
+    if (k != std::string::npos) return p.substr(0, k + 1);
+  }
+  return std::string();
+}
+
+static const std::vector<TuneRow>& tune_table() {
+  static std::vector<TuneRow> rows = [] {
+    std::vector<TuneRow> r;
+    const char* env = getenv("DTSORT_TUNE_FILE");
+    const std::string path = env ? std::string(env) : lib_dir() + "tune_table.txt";
+    FILE* f = fopen(path.c_str(), "r");
+    if (!f) return r;
+    char line[512];
+    while (fgets(line, sizeof(line), f)) {
+      if (line[0] == '#') continue;
+      TuneRow t;
+      if (sscanf(line, "%d %d %d %d %d %d %d %d", &t.kb, &t.vb, &t.seg, &t.lo, &t.hi, &t.digit_bits, &t.cutoff,
+                 &t.tile) == 8)
+        r.push_back(t);
+    }
+    fclose(f);
+    return r;
+  }();
+  return rows;
+}
+
+struct Tuned {
+  int digit_bits, cutoff, tile;
+};
+
+static Tuned tuned_params(int kb, int vb, bool seg, size_t n) {
+  int lg = 0;
+  while (lg < 63 && (2ull << lg) <= n) ++lg;
+  for (const TuneRow& t : tune_table())
+    if (t.kb == kb && t.vb == vb && t.seg == (seg ? 1 : 0) && lg >= t.lo && lg <= t.hi)
+      return Tuned{t.digit_bits, t.cutoff, t.tile};
+  return Tuned{0, 0, 0};
+}
+
+// Resolved parameters of one call.
+struct Params {
+  int gover;        // digit-bit override (0 = automatic)
+  uint32_t cutoff;  // base-case threshold
+  int tile;         // scatter tile shape (LevelArgs::tile)
+};
+
+template <typename K, typename V>
+static Params resolve_params(const SortJob<K, V>& J) {
+  constexpr bool HV = HasVal<V>::value;
+  const dtsort_opts& o = J.o;
+  int gover = o.digit_bits, creq = o.lds_cutoff, tile = o.tile_shape;
+  if (o.tuned) {
+    const Tuned tp = tuned_params((int)sizeof(K), HV ? (int)sizeof(V) : 0, J.seg != nullptr, J.n);
+    if (gover <= 0) gover = tp.digit_bits;
+    if (creq <= 0) creq = tp.cutoff;
+    if (tile <= 0) tile = tp.tile;
+  }
+  Params p;
+  p.gover = gover;
+  p.cutoff = cutoff_for((int)sizeof(K), HV, creq);
+  p.tile = tile > 0 ? tile - 1 : 0;
+  return p;
 }
 
 template <typename K, typename V>
@@ -218,6 +315,23 @@ static void fill_caps(LevelArgs& a, uint32_t n_tasks, uint64_t total, int gmax, 
   a.caps.merges = (uint32_t)std::min<uint64_t>((uint64_t)n_tasks << (gmax - 1), total + 1);
   a.caps.munits = (uint32_t)(total / 4096 + a.caps.merges + 1);
   a.caps.spills = (uint32_t)(total / (1u << 20) + a.caps.merges + 1);
+}
+
+static void add_stats(dtsort_stats* st, const LevelCounters& h, bool level) {
+  if (!st) return;
+  if (level) {
+    st->levels += h.st_tasks ? 1 : 0;
+    st->tasks += h.st_tasks;
+    st->records_distributed += h.st_distributed;
+    st->heavy_keys += h.st_heavy_keys;
+    st->heavy_records += h.st_heavy_records;
+    st->merges += h.merges;
+    st->records_merged += h.st_merge_records;
+    st->records_copied += h.st_copy_records;
+    st->overflow_records += h.st_overflow_records;
+  }
+  for (int k = 0; k < LEAF_CLASSES; ++k) st->leaf_sorts += h.leaf[k];
+  st->records_leaf_sorted += h.st_leaf_records;
 }
 
 struct LearnedInfoH {
@@ -284,9 +398,9 @@ static int learned_root(Ctx* c, SortJob<K, V>& J, LevelArgs& a, hipStream_t s, v
   J2.key_bits = J.key_bits;
   dtsort_default_opts(&J2.o);
   J2.o.seed = o.seed;
-  if ((r = ensure(c->inner->tk, dtsort_workspace_bytes((int)sizeof(K), 0, N), s))) return r;
+  if ((r = ensure(c->inner->w.tk, dtsort_workspace_bytes((int)sizeof(K), 0, N), s))) return r;
   J2.bufs.k[0] = samp;
-  J2.bufs.k[1] = (K*)c->inner->tk.p;
+  J2.bufs.k[1] = (K*)c->inner->w.tk.p;
   if ((r = run_sort<K, NoVal>(c->inner, J2, s, nullptr))) return r;
   mlp_data<K>(samp, N, J.key_bits, x, y, s);
   mlp_train(x, y, N, o.seed, steps, batch, lr, par, m, v, part, losses, s);
@@ -302,14 +416,10 @@ static int run_sort(Ctx* c, SortJob<K, V>& J, hipStream_t s, dtsort_stats* stats
   constexpr bool HV = HasVal<V>::value;
   const size_t n = J.n;
   const dtsort_opts& o = J.o;
-  int gover = o.digit_bits;
-  int creq = o.lds_cutoff;
-  if (o.tuned) {
-    Tuned tp = tuned_params((int)sizeof(K), HV, n);
-    if (gover <= 0) gover = tp.digit_bits;
-    if (creq <= 0) creq = tp.cutoff;
-  }
-  const uint32_t cutoff = cutoff_for((int)sizeof(K), HV, creq);
+  const Params P = resolve_params(J);
+  const int gover = P.gover;
+  const uint32_t cutoff = P.cutoff;
+  Work& W = c->w;
   LevelArgs a;
   std::memset(&a, 0, sizeof(a));
   a.seed = o.seed;
@@ -318,12 +428,14 @@ static int run_sort(Ctx* c, SortJob<K, V>& J, hipStream_t s, dtsort_stats* stats
   for (int k = 0; k < LEAF_CLASSES; ++k) a.leaf_max[k] = leaf_cap<K, V>(k);
   a.plain = o.mode == DTSORT_MODE_PLAIN;
   a.key_bits = J.key_bits;
+  a.tile = P.tile;
   if (stats) std::memset(stats, 0, sizeof(*stats));
 
   int r;
-  if ((r = ensure(c->ctr, sizeof(LevelCounters) * MAX_LEVELS + 256, s))) return r;
-  LevelCounters* dctr = (LevelCounters*)c->ctr.p;
-  void* d_info = (char*)c->ctr.p + sizeof(LevelCounters) * MAX_LEVELS;
+  // counters: [0] = the root (or seeding) step, [L + 1] = level L
+  if ((r = ensure(W.ctr, sizeof(LevelCounters) * (MAX_LEVELS + 1) + 256, s))) return r;
+  LevelCounters* dctr = (LevelCounters*)W.ctr.p;
+  void* d_info = (char*)W.ctr.p + sizeof(LevelCounters) * (MAX_LEVELS + 1);
   Prof prof;
   prof.on = o.profile != 0 && stats != nullptr;
   prof.s = s;
@@ -346,15 +458,15 @@ static int run_sort(Ctx* c, SortJob<K, V>& J, hipStream_t s, dtsort_stats* stats
     a.caps.tasks = J.n_seg + 1;
     a.caps.leaf = J.n_seg + 1;
     a.caps.copies = J.n_seg + 1;
-    if ((r = ensure(c->tasks[cur], sizeof(Task) * (size_t)a.caps.tasks, s))) return r;
+    if ((r = ensure(W.tasks[cur], sizeof(Task) * (size_t)a.caps.tasks, s))) return r;
     for (int k = 0; k < LEAF_CLASSES; ++k)
-      if ((r = ensure(c->leaf[k], sizeof(Leaf) * (size_t)a.caps.leaf, s))) return r;
-    if ((r = ensure(c->copies, sizeof(Leaf) * (size_t)a.caps.copies, s))) return r;
-    a.next = (Task*)c->tasks[cur].p;
-    for (int k = 0; k < LEAF_CLASSES; ++k) a.leaf[k] = (Leaf*)c->leaf[k].p;
-    a.copies = (Leaf*)c->copies.p;
+      if ((r = ensure(W.leaf[k], sizeof(Leaf) * (size_t)a.caps.leaf, s))) return r;
+    if ((r = ensure(W.copies, sizeof(Leaf) * (size_t)a.caps.copies, s))) return r;
+    a.next = (Task*)W.tasks[cur].p;
+    for (int k = 0; k < LEAF_CLASSES; ++k) a.leaf[k] = (Leaf*)W.leaf[k].p;
+    a.copies = (Leaf*)W.copies.p;
     a.ctr = dctr;
-    HIPCHK(hipMemsetAsync(dctr, 0, sizeof(LevelCounters), s));
+    launch_zero_counters(dctr, 1, s);
     launch_seed_segments<K, V>(a, J.seg, J.n_seg, n, s);
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(c->h_ctr, dctr, sizeof(LevelCounters), hipMemcpyDeviceToHost, s));
@@ -363,22 +475,21 @@ static int run_sort(Ctx* c, SortJob<K, V>& J, hipStream_t s, dtsort_stats* stats
     if (h.error & ERR_SEGMENTS) return fail(DTSORT_EINVAL, "segment offsets are not valid");
     if (h.error) return fail(DTSORT_EINTERNAL, "capacity check failed while seeding segments");
     prof.begin(PK_LEAF);
-    for (int k = 0; k < LEAF_CLASSES; ++k) launch_leaf<K, V>((Leaf*)c->leaf[k].p, h.leaf[k], k, J.bufs, s);
+    for (int k = 0; k < LEAF_CLASSES; ++k)
+      launch_leaf<K, V>((Leaf*)W.leaf[k].p, &dctr[0].leaf[k], a.caps.leaf, std::min(h.leaf[k], a.caps.leaf), k,
+                        J.bufs, s);
     prof.end(2.0 * rec_bytes * (double)h.st_leaf_records);
     HIPCHK(hipGetLastError());
-    if (stats) {
-      for (int k = 0; k < LEAF_CLASSES; ++k) stats->leaf_sorts += h.leaf[k];
-      stats->records_leaf_sorted += h.st_leaf_records;
-    }
+    add_stats(stats, h, false);
     n_tasks = h.next_tasks;
     total = h.next_records;
     max_size = h.next_max_size;
-    // the root leaves must finish before level 0 reuses the leaf lists: the
-    // next children step is enqueued after them on the same stream.
+    // the root leaves run before level 0 reuses the leaf lists: its child
+    // planning is enqueued after them on the same stream.
   } else {
     if (n <= 1) return 0;
     if (n <= cutoff) {
-      if ((r = ensure(c->leaf[0], sizeof(Leaf), s))) return r;
+      if ((r = ensure(W.leaf[0], sizeof(Leaf), s))) return r;
       Leaf* hl = (Leaf*)c->h_stage;
       HIPCHK(hipStreamSynchronize(s));  // staging buffer reuse
       hl->off = 0;
@@ -387,30 +498,20 @@ static int run_sort(Ctx* c, SortJob<K, V>& J, hipStream_t s, dtsort_stats* stats
       hl->from = 0;
       hl->to = 0;
       hl->pad = 0;
-      HIPCHK(hipMemcpyAsync(c->leaf[0].p, hl, sizeof(Leaf), hipMemcpyHostToDevice, s));
+      uint32_t* one = (uint32_t*)((char*)c->h_stage + 64);
+      *one = 1;
+      HIPCHK(hipMemcpyAsync(W.leaf[0].p, hl, sizeof(Leaf), hipMemcpyHostToDevice, s));
+      HIPCHK(hipMemcpyAsync(&dctr[0].leaf[0], one, 4, hipMemcpyHostToDevice, s));
       int cls = LEAF_CLASSES - 1;
       for (int k = LEAF_CLASSES - 2; k >= 0; --k)
         if (n <= leaf_cap<K, V>(k)) cls = k;
-      launch_leaf<K, V>((Leaf*)c->leaf[0].p, 1, cls, J.bufs, s);
+      launch_leaf<K, V>((Leaf*)W.leaf[0].p, &dctr[0].leaf[0], 1, 1, cls, J.bufs, s);
       HIPCHK(hipGetLastError());
       if (stats) stats->leaf_sorts = 1, stats->records_leaf_sorted = n;
       return 0;
     }
-    if ((r = ensure(c->tasks[cur], sizeof(Task), s))) return r;
-    Task* ht = (Task*)c->h_stage;
-    HIPCHK(hipStreamSynchronize(s));
-    std::memset(ht, 0, sizeof(Task));
-    ht->off = 0;
-    ht->size = (uint32_t)n;
-    ht->n_root = (uint32_t)n;
-    ht->level = 0;
-    ht->hi = (uint8_t)J.key_bits;
-    ht->src = 0;
-    ht->tgt = 0;
-    ht->flags = 0;
-    ht->gamma = (uint8_t)plan_gamma((uint32_t)n, gover);
-    (void)learned;
-    HIPCHK(hipMemcpyAsync(c->tasks[cur].p, ht, sizeof(Task), hipMemcpyHostToDevice, s));
+    if ((r = ensure(W.tasks[cur], sizeof(Task), s))) return r;
+    launch_root<K>((Task*)W.tasks[cur].p, dctr, n, J.key_bits, plan_gamma((uint32_t)n, gover), s);
     n_tasks = 1;
     total = n;
     max_size = (uint32_t)n;
@@ -421,7 +522,8 @@ static int run_sort(Ctx* c, SortJob<K, V>& J, hipStream_t s, dtsort_stats* stats
   for (; n_tasks > 0; ++L) {
     if (L >= MAX_LEVELS) return fail(DTSORT_EINTERNAL, "recursion deeper than expected");
     const int gmax = plan_gamma(max_size, gover);
-    // chunk: a multiple of 8192 records aiming at ~2048 units per level
+    // chunk: a multiple of 8192 records aiming at ~2048 units per level (the
+    // prep kernel derives the same value when it is left 0)
     uint64_t chunk = (total + 2047) / 2048;
     chunk = std::max<uint64_t>(8192, (chunk + 8191) / 8192 * 8192);
     const uint64_t units = total / chunk + n_tasks + 1;
@@ -430,36 +532,38 @@ static int run_sort(Ctx* c, SortJob<K, V>& J, hipStream_t s, dtsort_stats* stats
     const uint64_t tab_bytes = (uint64_t)n_tasks * sl.bytes;
     const uint32_t cols = dist_cols(gmax);
     const uint64_t cm_entries = units * cols * (uint64_t)nb_cap(gmax);
-    LevelKeep& K_ = c->lv[L];
+    LevelKeep& K_ = W.lv[L];
     fill_caps<K, V>(a, n_tasks, total, gmax, cutoff);
     a.caps.units = (uint32_t)units;
     a.caps.cm = cm_entries;
     a.caps.tab = tab_bytes;
-    if ((r = ensure(c->units, sizeof(uint2) * units, s))) return r;
-    if ((r = ensure(c->cm, 4 * cm_entries, s))) return r;
+    if ((r = ensure(W.units, sizeof(uint2) * units, s))) return r;
+    if ((r = ensure(W.cm, 4 * cm_entries, s))) return r;
     if ((r = ensure(K_.tab, tab_bytes, s))) return r;
-    if ((r = ensure(c->tasks[1 - cur], sizeof(Task) * (size_t)a.caps.tasks, s))) return r;
+    if ((r = ensure(W.tasks[1 - cur], sizeof(Task) * (size_t)a.caps.tasks, s))) return r;
     for (int k = 0; k < LEAF_CLASSES; ++k)
-      if ((r = ensure(c->leaf[k], sizeof(Leaf) * (size_t)a.caps.leaf, s))) return r;
-    if ((r = ensure(c->copies, sizeof(Leaf) * (size_t)a.caps.copies, s))) return r;
+      if ((r = ensure(W.leaf[k], sizeof(Leaf) * (size_t)a.caps.leaf, s))) return r;
+    if ((r = ensure(W.copies, sizeof(Leaf) * (size_t)a.caps.copies, s))) return r;
     if ((r = ensure(K_.merges, sizeof(Merge) * (size_t)a.caps.merges, s))) return r;
     if ((r = ensure(K_.munits, sizeof(uint2) * (size_t)a.caps.munits, s))) return r;
     if ((r = ensure(K_.spills, sizeof(Leaf) * (size_t)a.caps.spills, s))) return r;
-    a.tasks = (Task*)c->tasks[cur].p;
+    a.tasks = (Task*)W.tasks[cur].p;
     a.n_tasks = n_tasks;
     a.chunk = (uint32_t)chunk;
-    a.units = (uint2*)c->units.p;
+    a.units = (uint2*)W.units.p;
     a.tab = (uint8_t*)K_.tab.p;
     a.slot_bytes = sl.bytes;
     a.cols = cols;
-    a.cm = (uint32_t*)c->cm.p;
-    a.next = (Task*)c->tasks[1 - cur].p;
-    for (int k = 0; k < LEAF_CLASSES; ++k) a.leaf[k] = (Leaf*)c->leaf[k].p;
-    a.copies = (Leaf*)c->copies.p;
+    a.cm = (uint32_t*)W.cm.p;
+    a.next = (Task*)W.tasks[1 - cur].p;
+    for (int k = 0; k < LEAF_CLASSES; ++k) a.leaf[k] = (Leaf*)W.leaf[k].p;
+    a.copies = (Leaf*)W.copies.p;
     a.merges = (Merge*)K_.merges.p;
     a.spills = (Leaf*)K_.spills.p;
-    a.ctr = dctr + L;
-    HIPCHK(hipMemsetAsync(a.ctr, 0, sizeof(LevelCounters), s));
+    a.in = dctr + L;
+    a.ctr = dctr + L + 1;
+    a.grid_tasks = n_tasks;
+    a.grid_units = (uint32_t)units;
     launch_prep(a, s);
     prof.begin(PK_PLAN);
     launch_plan<K>(a, J.bufs.k[0], J.bufs.k[1], s);
@@ -485,9 +589,9 @@ static int run_sort(Ctx* c, SortJob<K, V>& J, hipStream_t s, dtsort_stats* stats
     launch_children<K, V>(a, J.bufs, s);
     prof.end(0.0);
     HIPCHK(hipGetLastError());
-    HIPCHK(hipMemcpyAsync(c->h_ctr + L, a.ctr, sizeof(LevelCounters), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(c->h_ctr + L + 1, a.ctr, sizeof(LevelCounters), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    const LevelCounters h = c->h_ctr[L];
+    const LevelCounters h = c->h_ctr[L + 1];
     if (h.error) return fail(DTSORT_EINTERNAL, "device capacity check failed (flags " + std::to_string(h.error) + ")");
     if (learn_here && stats) {
       LearnedInfoH li;
@@ -503,30 +607,20 @@ static int run_sort(Ctx* c, SortJob<K, V>& J, hipStream_t s, dtsort_stats* stats
     if (le0) (void)hipEventDestroy(le0), le0 = nullptr;
     if (le1) (void)hipEventDestroy(le1), le1 = nullptr;
     prof.begin(PK_LEAF);
-    for (int k = 0; k < LEAF_CLASSES; ++k) launch_leaf<K, V>((Leaf*)c->leaf[k].p, h.leaf[k], k, J.bufs, s);
+    for (int k = 0; k < LEAF_CLASSES; ++k)
+      launch_leaf<K, V>((Leaf*)W.leaf[k].p, &a.ctr->leaf[k], a.caps.leaf, h.leaf[k], k, J.bufs, s);
     prof.end(2.0 * rec_bytes * (double)h.st_leaf_records);
     prof.begin(PK_COPY);
-    launch_copy<K, V>((Leaf*)c->copies.p, h.copies, J.bufs, s);
+    launch_copy<K, V>((Leaf*)W.copies.p, &a.ctr->copies, a.caps.copies, h.copies, J.bufs, s);
     prof.end(2.0 * rec_bytes * (double)h.st_copy_records);
     K_.n_merges = h.merges;
     K_.n_munits = h.merge_units;
     K_.n_spills = h.spills;
+    K_.caps = a.caps;
     K_.merge_records = (double)h.st_merge_records;
-    launch_merge_units((Merge*)K_.merges.p, h.merges, (uint2*)K_.munits.p, s);
+    launch_merge_units((Merge*)K_.merges.p, &a.ctr->merges, a.caps.merges, h.merges, (uint2*)K_.munits.p, s);
     HIPCHK(hipGetLastError());
-    if (stats) {
-      stats->levels += 1;
-      stats->tasks += h.st_tasks;
-      stats->records_distributed += h.st_distributed;
-      stats->heavy_keys += h.st_heavy_keys;
-      stats->heavy_records += h.st_heavy_records;
-      stats->merges += h.merges;
-      stats->records_merged += h.st_merge_records;
-      for (int k = 0; k < LEAF_CLASSES; ++k) stats->leaf_sorts += h.leaf[k];
-      stats->records_leaf_sorted += h.st_leaf_records;
-      stats->records_copied += h.st_copy_records;
-      stats->overflow_records += h.st_overflow_records;
-    }
+    add_stats(stats, h, true);
     n_tasks = h.next_tasks;
     total = h.next_records;
     max_size = h.next_max_size;
@@ -534,16 +628,276 @@ static int run_sort(Ctx* c, SortJob<K, V>& J, hipStream_t s, dtsort_stats* stats
   }
   // ---- dovetail merges, deepest level first
   for (int l = L - 1; l >= 0; --l) {
-    LevelKeep& K_ = c->lv[l];
+    LevelKeep& K_ = W.lv[l];
     if (K_.n_merges == 0) continue;
+    LevelCounters* lc = dctr + l + 1;
     prof.begin(PK_MERGE);
-    launch_copy<K, V>((Leaf*)K_.spills.p, K_.n_spills, J.bufs, s);
-    launch_merge<K, V>((Merge*)K_.merges.p, K_.n_merges, (uint2*)K_.munits.p, K_.n_munits, (uint8_t*)K_.tab.p,
-                       J.bufs, s);
+    launch_copy<K, V>((Leaf*)K_.spills.p, &lc->spills, K_.caps.spills, K_.n_spills, J.bufs, s);
+    launch_merge<K, V>((Merge*)K_.merges.p, &lc->merges, K_.caps.merges, K_.n_merges, (uint2*)K_.munits.p,
+                       &lc->merge_units, K_.caps.munits, K_.n_munits, (uint8_t*)K_.tab.p, J.bufs, s);
     prof.end(2.0 * rec_bytes * K_.merge_records);
     HIPCHK(hipGetLastError());
   }
   prof.finish(stats);
+  return 0;
+}
+
+// ------------------------------------------------------------ graph form
+// The whole schedule with no host read-back: every level's kernels read
+// their work counts on the device and loop with a grid stride over
+// persistent grids; every list is sized for the worst case of n records, and
+// the number of levels is the bound below.  Recorded once into a HIP graph.
+struct GPlan {
+  int gmax = 8, levels = 0;
+  uint32_t cutoff = 0;
+  Caps caps{};
+  uint64_t tab_bytes = 0;
+  uint32_t slot_bytes = 0;
+  uint32_t grid_tasks = 0, grid_units = 0, grid_leaf[LEAF_CLASSES] = {}, grid_copy = 0, grid_mpos = 0,
+           grid_munit = 0, grid_spill = 0;
+};
+
+template <typename K, typename V>
+static GPlan graph_plan(const SortJob<K, V>& J, const Params& P) {
+  GPlan g;
+  const uint64_t n = std::max<uint64_t>(J.n, 2);
+  g.gmax = plan_gamma((uint32_t)std::min<uint64_t>(n, 0xFFFFFFFFu), P.gover);
+  g.cutoff = P.cutoff;
+  // Each light child consumes at least one digit of the smallest width and an
+  // overflow child is followed by a level that does, so two levels remove at
+  // least gmin bits; one more level covers the last-digit step.
+  const int gmin = P.gover > 0 ? std::max(1, std::min(P.gover, GMAX)) : 8;
+  g.levels = std::min(MAX_LEVELS, 2 * ((J.key_bits + gmin - 1) / gmin) + 2);
+  const uint64_t nbc = (uint64_t)nb_cap(g.gmax);
+  const uint64_t tasks = n / (g.cutoff + 1ull) + 1;
+  Caps& c = g.caps;
+  c.tasks = (uint32_t)tasks;
+  c.leaf = (uint32_t)std::min<uint64_t>(tasks * nbc + J.n_seg + 1, n + 1);
+  c.copies = (uint32_t)std::min<uint64_t>(tasks * nbc + n / (1u << 20) + 1, n + 1);
+  c.merges = (uint32_t)std::min<uint64_t>(tasks << (g.gmax - 1), n + 1);
+  c.munits = (uint32_t)(n / 4096 + c.merges + 1);
+  c.spills = (uint32_t)(n / (1u << 20) + c.merges + 1);
+  c.units = (uint32_t)(n / 8192 + tasks + 1);
+  c.cm = (uint64_t)c.units * nbc;
+  const SlotLayout sl = slot_layout(g.gmax, false);
+  g.slot_bytes = sl.bytes;
+  g.tab_bytes = tasks * sl.bytes;
+  c.tab = g.tab_bytes;
+  auto pg = [](uint32_t per_cu, uint64_t cap) { return (uint32_t)std::min<uint64_t>(persistent_grid(per_cu), cap); };
+  g.grid_tasks = pg(4, c.tasks);
+  g.grid_units = pg(8, c.units);
+  const uint32_t per_cu[LEAF_CLASSES] = {16, 8, 4, 2, 2};
+  for (int k = 0; k < LEAF_CLASSES; ++k) g.grid_leaf[k] = pg(per_cu[k], c.leaf);
+  g.grid_copy = pg(4, c.copies);
+  g.grid_mpos = pg(8, c.merges);
+  g.grid_munit = pg(4, c.munits);
+  g.grid_spill = pg(4, c.spills);
+  return g;
+}
+
+template <typename K, typename V>
+static int graph_alloc(Work& W, const GPlan& g, hipStream_t s) {
+  int r;
+  const Caps& c = g.caps;
+  if ((r = ensure(W.ctr, sizeof(LevelCounters) * (g.levels + 1), s))) return r;
+  for (auto& b : W.tasks)
+    if ((r = ensure(b, sizeof(Task) * (size_t)c.tasks, s))) return r;
+  if ((r = ensure(W.units, sizeof(uint2) * (size_t)c.units, s))) return r;
+  if ((r = ensure(W.cm, 4 * c.cm, s))) return r;
+  for (auto& b : W.leaf)
+    if ((r = ensure(b, sizeof(Leaf) * (size_t)c.leaf, s))) return r;
+  if ((r = ensure(W.copies, sizeof(Leaf) * (size_t)c.copies, s))) return r;
+  W.lv.resize(g.levels);
+  for (int L = 0; L < g.levels; ++L) {
+    LevelKeep& K_ = W.lv[L];
+    if ((r = ensure(K_.tab, g.tab_bytes, s))) return r;
+    if ((r = ensure(K_.merges, sizeof(Merge) * (size_t)c.merges, s))) return r;
+    if ((r = ensure(K_.munits, sizeof(uint2) * (size_t)c.munits, s))) return r;
+    if ((r = ensure(K_.spills, sizeof(Leaf) * (size_t)c.spills, s))) return r;
+    K_.caps = c;
+  }
+  return 0;
+}
+
+// Enqueue the whole schedule on `s` (recordable: kernels only).
+template <typename K, typename V>
+static void graph_enqueue(Work& W, const GPlan& g, const SortJob<K, V>& J, const Params& P, hipStream_t s) {
+  LevelArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.seed = J.o.seed;
+  a.g_override = P.gover;
+  a.cutoff = g.cutoff;
+  for (int k = 0; k < LEAF_CLASSES; ++k) a.leaf_max[k] = leaf_cap<K, V>(k);
+  a.plain = J.o.mode == DTSORT_MODE_PLAIN;
+  a.key_bits = J.key_bits;
+  a.tile = P.tile;
+  a.caps = g.caps;
+  LevelCounters* dctr = (LevelCounters*)W.ctr.p;
+  for (int k = 0; k < LEAF_CLASSES; ++k) a.leaf[k] = (Leaf*)W.leaf[k].p;
+  a.copies = (Leaf*)W.copies.p;
+  launch_zero_counters(dctr, (uint32_t)g.levels + 1, s);
+  if (J.seg) {
+    a.next = (Task*)W.tasks[0].p;
+    a.ctr = dctr;
+    launch_seed_segments<K, V>(a, J.seg, J.n_seg, J.n, s);
+    for (int k = 0; k < LEAF_CLASSES; ++k)
+      launch_leaf<K, V>((Leaf*)W.leaf[k].p, &dctr[0].leaf[k], g.caps.leaf, g.grid_leaf[k], k, J.bufs, s);
+  } else {
+    launch_root<K>((Task*)W.tasks[0].p, dctr, J.n, J.key_bits, plan_gamma((uint32_t)J.n, P.gover), s);
+  }
+  for (int L = 0; L < g.levels; ++L) {
+    LevelKeep& K_ = W.lv[L];
+    a.tasks = (Task*)W.tasks[L & 1].p;
+    a.next = (Task*)W.tasks[(L + 1) & 1].p;
+    a.n_tasks = g.caps.tasks;
+    a.chunk = 0;
+    a.units = (uint2*)W.units.p;
+    a.tab = (uint8_t*)K_.tab.p;
+    a.slot_bytes = g.slot_bytes;
+    a.cols = 1;
+    a.cm = (uint32_t*)W.cm.p;
+    a.merges = (Merge*)K_.merges.p;
+    a.spills = (Leaf*)K_.spills.p;
+    a.in = dctr + L;
+    a.ctr = dctr + L + 1;
+    a.grid_tasks = g.grid_tasks;
+    a.grid_units = g.grid_units;
+    launch_prep(a, s);
+    launch_plan<K>(a, J.bufs.k[0], J.bufs.k[1], s);
+    launch_distribute<K, V>(a, J.bufs, g.gmax, 0x7FFFFFFFu, s, -1);
+    launch_children<K, V>(a, J.bufs, s);
+    for (int k = 0; k < LEAF_CLASSES; ++k)
+      launch_leaf<K, V>((Leaf*)W.leaf[k].p, &a.ctr->leaf[k], g.caps.leaf, g.grid_leaf[k], k, J.bufs, s);
+    launch_copy<K, V>((Leaf*)W.copies.p, &a.ctr->copies, g.caps.copies, g.grid_copy, J.bufs, s);
+    launch_merge_units((Merge*)K_.merges.p, &a.ctr->merges, g.caps.merges, g.grid_mpos, (uint2*)K_.munits.p, s);
+  }
+  for (int L = g.levels - 1; L >= 0; --L) {
+    LevelKeep& K_ = W.lv[L];
+    LevelCounters* lc = dctr + L + 1;
+    launch_copy<K, V>((Leaf*)K_.spills.p, &lc->spills, g.caps.spills, g.grid_spill, J.bufs, s);
+    launch_merge<K, V>((Merge*)K_.merges.p, &lc->merges, g.caps.merges, g.grid_mpos, (uint2*)K_.munits.p,
+                       &lc->merge_units, g.caps.munits, g.grid_munit, (uint8_t*)K_.tab.p, J.bufs, s);
+  }
+}
+
+struct GraphKey {
+  int kb, vb;
+  const void *k, *v, *ws;
+  size_t n;
+  const uint64_t* seg;
+  uint32_t n_seg;
+  uint64_t seed;
+  int key_bits, mode, gover, tile;
+  uint32_t cutoff;
+  bool operator==(const GraphKey& o) const {
+    return kb == o.kb && vb == o.vb && k == o.k && v == o.v && ws == o.ws && n == o.n && seg == o.seg &&
+           n_seg == o.n_seg && seed == o.seed && key_bits == o.key_bits && mode == o.mode && gover == o.gover &&
+           tile == o.tile && cutoff == o.cutoff;
+  }
+};
+
+struct GraphEntry {
+  GraphKey key;
+  Work w;
+  hipGraph_t g = nullptr;
+  hipGraphExec_t x = nullptr;
+  int levels = 0;
+  uint64_t used = 0;
+};
+
+constexpr size_t MAX_GRAPHS = 4;
+
+static void free_graph(GraphEntry* e) {
+  if (e->x) (void)hipGraphExecDestroy(e->x);
+  if (e->g) (void)hipGraphDestroy(e->g);
+  free_work(e->w);
+  delete e;
+}
+
+template <typename K, typename V>
+static int graph_sort(Ctx* c, SortJob<K, V>& J, void* user_ws, hipStream_t s, dtsort_stats* stats) {
+  constexpr bool HV = HasVal<V>::value;
+  const Params P = resolve_params(J);
+  GraphKey key;
+  std::memset(&key, 0, sizeof(key));
+  key.kb = (int)sizeof(K);
+  key.vb = HV ? (int)sizeof(V) : 0;
+  key.k = J.bufs.k[0];
+  if constexpr (HV) key.v = J.bufs.v[0];
+  key.ws = user_ws;
+  key.n = J.n;
+  key.seg = J.seg;
+  key.n_seg = J.n_seg;
+  key.seed = J.o.seed;
+  key.key_bits = J.key_bits;
+  key.mode = J.o.mode;
+  key.gover = P.gover;
+  key.tile = P.tile;
+  key.cutoff = P.cutoff;
+  GraphEntry* e = nullptr;
+  for (GraphEntry* x : c->graphs)
+    if (x->key == key) e = x;
+  const GPlan g = graph_plan(J, P);
+  int r;
+  if (!e) {
+    if (c->graphs.size() >= MAX_GRAPHS) {
+      auto it = std::min_element(c->graphs.begin(), c->graphs.end(),
+                                 [](const GraphEntry* p, const GraphEntry* q) { return p->used < q->used; });
+      HIPCHK(hipStreamSynchronize(s));
+      HIPCHK(hipDeviceSynchronize());
+      free_graph(*it);
+      c->graphs.erase(it);
+    }
+    if (!c->cap_stream) HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    e = new GraphEntry();
+    e->key = key;
+    e->levels = g.levels;
+    hipStream_t cs = c->cap_stream;
+    if ((r = graph_alloc<K, V>(e->w, g, cs)) == 0 && !user_ws) {
+      r = ensure(e->w.tk, dtsort_workspace_bytes((int)sizeof(K), HV ? (int)sizeof(V) : 0, J.n), cs);
+    }
+    if (r) {
+      free_graph(e);
+      return r;
+    }
+    HIPCHK(hipStreamSynchronize(cs));
+    SortJob<K, V> J2 = J;
+    if (!user_ws) {
+      char* ws = (char*)e->w.tk.p;
+      J2.bufs.k[1] = (K*)ws;
+      if constexpr (HV) J2.bufs.v[1] = (V*)(ws + ((J.n * sizeof(K) + 255) & ~(size_t)255));
+    }
+    (void)persistent_grid(1);  // device query outside the recording
+    hipError_t ce = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (ce == hipSuccess) {
+      graph_enqueue<K, V>(e->w, g, J2, P, cs);
+      const hipError_t le = hipGetLastError();
+      ce = hipStreamEndCapture(cs, &e->g);
+      if (ce == hipSuccess) ce = le;
+    }
+    if (ce == hipSuccess) ce = hipGraphInstantiate(&e->x, e->g, nullptr, nullptr, 0);
+    if (ce != hipSuccess) {
+      free_graph(e);
+      return fail(DTSORT_EHIP, std::string("graph recording failed: ") + hipGetErrorString(ce));
+    }
+    c->graphs.push_back(e);
+  }
+  e->used = ++c->clock;
+  HIPCHK(hipGraphLaunch(e->x, s));
+  if (stats) {
+    std::memset(stats, 0, sizeof(*stats));
+    std::vector<LevelCounters> h(e->levels + 1);
+    HIPCHK(hipMemcpyAsync(h.data(), e->w.ctr.p, sizeof(LevelCounters) * h.size(), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    uint32_t err = 0;
+    for (size_t L = 0; L < h.size(); ++L) {
+      err |= h[L].error;
+      add_stats(stats, h[L], L > 0);
+    }
+    if (h.back().next_tasks) err |= ERR_TASKS;  // work left after the last recorded level
+    if (err & ERR_SEGMENTS) return fail(DTSORT_EINVAL, "segment offsets are not valid");
+    if (err) return fail(DTSORT_EINTERNAL, "device capacity check failed (flags " + std::to_string(err) + ")");
+  }
   return 0;
 }
 
@@ -569,7 +923,10 @@ static int sort_entry(K* keys, V* vals, size_t n, const uint64_t* seg, size_t n_
   int key_bits = o.key_bits > 0 ? o.key_bits : kbits;
   if (key_bits > kbits) return fail(DTSORT_EINVAL, "key_bits larger than the key width");
   if (o.mode < 0 || o.mode > 2) return fail(DTSORT_EINVAL, "unknown mode");
-  if (o.digit_bits < 0 || o.digit_bits > 16) return fail(DTSORT_EINVAL, "digit_bits out of range");
+  if (o.digit_bits < 0 || o.digit_bits > GMAX) return fail(DTSORT_EINVAL, "digit_bits out of range");
+  if (o.tile_shape < 0 || o.tile_shape > 4) return fail(DTSORT_EINVAL, "tile_shape out of range");
+  if (o.graph && (o.mode == DTSORT_MODE_LEARNED || o.profile))
+    return fail(DTSORT_EINVAL, "graph mode does not combine with LEARNED mode or profiling");
   if (seg && n_seg == 0) return 0;
   if (!seg && n <= 1) return 0;
   if (seg && n_seg >= (1ull << 31)) return fail(DTSORT_EINVAL, "too many segments");
@@ -589,17 +946,26 @@ static int sort_entry(K* keys, V* vals, size_t n, const uint64_t* seg, size_t n_
   if constexpr (HV) J.bufs.v[0] = vals;
   // ping-pong partner
   const size_t need = dtsort_workspace_bytes((int)sizeof(K), HV ? (int)sizeof(V) : 0, n);
-  char* ws;
+  char* ws = nullptr;
   if (o.workspace) {
     if (o.workspace_bytes < need) return fail(DTSORT_EWORKSPACE, "workspace smaller than dtsort_workspace_bytes()");
     ws = (char*)o.workspace;
-  } else {
-    if ((r = ensure(c->tk, need, s))) return r;
-    ws = (char*)c->tk.p;
   }
-  J.bufs.k[1] = (K*)ws;
-  if constexpr (HV) J.bufs.v[1] = (V*)(ws + ((n * sizeof(K) + 255) & ~(size_t)255));
-  r = run_sort<K, V>(c, J, s, o.stats);
+  if (o.graph) {
+    if (ws) {
+      J.bufs.k[1] = (K*)ws;
+      if constexpr (HV) J.bufs.v[1] = (V*)(ws + ((n * sizeof(K) + 255) & ~(size_t)255));
+    }
+    r = graph_sort<K, V>(c, J, ws, s, o.stats);
+  } else {
+    if (!ws) {
+      if ((r = ensure(c->w.tk, need, s))) return r;
+      ws = (char*)c->w.tk.p;
+    }
+    J.bufs.k[1] = (K*)ws;
+    if constexpr (HV) J.bufs.v[1] = (V*)(ws + ((n * sizeof(K) + 255) & ~(size_t)255));
+    r = run_sort<K, V>(c, J, s, o.stats);
+  }
   if (hipEventRecord(c->done, s) == hipSuccess) {
     c->has_last = true;
     c->last_stream = s;
@@ -644,52 +1010,26 @@ int dtsort_segmented(uint32_t* keys, uint32_t* values, size_t n_total, const uin
   return sort_entry<uint32_t, NoVal>(keys, (NoVal*)nullptr, n_total, seg_offsets, n_segments, opts, stream);
 }
 
+static void free_ctx(Ctx* c) {
+  free_work(c->w);
+  free_buf(c->lrn);
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  for (GraphEntry* e : c->graphs) free_graph(e);
+  c->graphs.clear();
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  if (c->inner) free_ctx(c->inner);
+  if (c->h_ctr) (void)hipHostFree(c->h_ctr);
+  if (c->h_stage) (void)hipHostFree(c->h_stage);
+  if (c->done) (void)hipEventDestroy(c->done);
+  delete c;
+}
+
 void dtsort_release(void) {
   std::lock_guard<std::mutex> lk(g_mu);
   for (Ctx* c : g_ctx) {
     if (!c) continue;
     (void)hipDeviceSynchronize();
-    free_buf(c->tk);
-    free_buf(c->tv);
-    for (auto& b : c->tasks) free_buf(b);
-    free_buf(c->units);
-    free_buf(c->cm);
-    for (auto& b : c->leaf) free_buf(b);
-    free_buf(c->copies);
-    free_buf(c->ctr);
-    free_buf(c->scratch);
-    for (auto& l : c->lv) {
-      free_buf(l.tab);
-      free_buf(l.merges);
-      free_buf(l.munits);
-      free_buf(l.spills);
-    }
-    free_buf(c->lrn);
-    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
-    if (c->inner) {
-      Ctx* in = c->inner;
-      free_buf(in->tk);
-      for (auto& b : in->tasks) free_buf(b);
-      free_buf(in->units);
-      free_buf(in->cm);
-      for (auto& b : in->leaf) free_buf(b);
-      free_buf(in->copies);
-      free_buf(in->ctr);
-      for (auto& l : in->lv) {
-        free_buf(l.tab);
-        free_buf(l.merges);
-        free_buf(l.munits);
-        free_buf(l.spills);
-      }
-      if (in->h_ctr) (void)hipHostFree(in->h_ctr);
-      if (in->h_stage) (void)hipHostFree(in->h_stage);
-      if (in->done) (void)hipEventDestroy(in->done);
-      delete in;
-    }
-    if (c->h_ctr) (void)hipHostFree(c->h_ctr);
-    if (c->h_stage) (void)hipHostFree(c->h_stage);
-    if (c->done) (void)hipEventDestroy(c->done);
-    delete c;
+    free_ctx(c);
   }
   g_ctx.clear();
 }

@@ -27,9 +27,11 @@ __global__ __launch_bounds__(1024) void k_plan(LevelArgs a, const K* k0, const K
   __shared__ uint32_t tmp[T / WAVE + 1];
   __shared__ int s_top, s_w, s_shift;
 
-  Task& tr = a.tasks[blockIdx.x];
+  const uint32_t n_tasks = a.ctr->cur_tasks;
+  for (uint32_t ti = blockIdx.x; ti < n_tasks; ti += gridDim.x) {
+  Task& tr = a.tasks[ti];
   const Task t = tr;
-  if (t.flags & TF_LEARNED) return;  // planned by the learned-partitioner step
+  if (t.flags & TF_LEARNED) continue;  // planned by the learned-partitioner step
   const int g = t.gamma;
   const int hi = t.hi;
   const SlotLayout sl = slot_layout(g, false);
@@ -130,18 +132,20 @@ __global__ __launch_bounds__(1024) void k_plan(LevelArgs a, const K* k0, const K
     tr.n_heavy = (uint16_t)nh;
     tr.n_buckets = (uint16_t)(zones + nh + 1);
   }
+  __syncthreads();
+  }
 }
 
 template <typename K>
 void launch_plan(const LevelArgs& a, const K* k0, const K* k1, hipStream_t s) {
-  hipLaunchKernelGGL(k_plan<K>, dim3(a.n_tasks), dim3(1024), 0, s, a, k0, k1);
+  hipLaunchKernelGGL(k_plan<K>, dim3(a.grid_tasks), dim3(1024), 0, s, a, k0, k1);
 }
 
 // ---------------------------------------------------------------- leaves
 // Base case: a stable radix sort in LDS of a subproblem of at most T*ITEMS
 // records, only over the bit range in which its keys differ.
 template <typename K, typename V, int T, int ITEMS, int RANKREQ>
-__global__ __launch_bounds__(T) void k_leaf(const Leaf* items, Bufs<K, V> bf) {
+__global__ __launch_bounds__(T) void k_leaf(const Leaf* items, const uint32_t* count, uint32_t cap, Bufs<K, V> bf) {
   constexpr int N = T * ITEMS;
   constexpr bool HV = HasVal<V>::value;
   __shared__ K sk[N];
@@ -156,7 +160,9 @@ __global__ __launch_bounds__(T) void k_leaf(const Leaf* items, Bufs<K, V> bf) {
   if constexpr (USE_LDS) {
     for (int i = threadIdx.x; i < bsort_match_words<T>(); i += T) mk[i] = 0ull;
   }
-  const Leaf it = items[blockIdx.x];
+  const uint32_t n_items = min(*count, cap);
+  for (uint32_t li = blockIdx.x; li < n_items; li += gridDim.x) {
+  const Leaf it = items[li];
   const K* kin = bf.k[it.from] + it.off;
   K* kout = bf.k[it.to] + it.off;
   const int n = (int)it.size;
@@ -196,6 +202,8 @@ __global__ __launch_bounds__(T) void k_leaf(const Leaf* items, Bufs<K, V> bf) {
       if (e < n) vout[e] = vv[i];
     }
   }
+  __syncthreads();
+  }
 }
 
 // Ranking mode of the leaf sorts (tuning knob: DTSORT_LEAF_RANK=ballot|lds).
@@ -211,47 +219,50 @@ static int leaf_rank_mode() {
 }
 
 template <typename K, typename V, int RANK>
-static void launch_leaf_r(const Leaf* items, uint32_t n_items, int cls, Bufs<K, V> b, hipStream_t s) {
+static void launch_leaf_r(const Leaf* items, const uint32_t* count, uint32_t cap, uint32_t grid, int cls,
+                          Bufs<K, V> b, hipStream_t s) {
   constexpr bool big8 = sizeof(K) == 8 && HasVal<V>::value;
   switch (cls) {
     case 0:
-      hipLaunchKernelGGL((k_leaf<K, V, 64, 4, RANK>), dim3(n_items), dim3(64), 0, s, items, b);
+      hipLaunchKernelGGL((k_leaf<K, V, 64, 4, RANK>), dim3(grid), dim3(64), 0, s, items, count, cap, b);
       break;
     case 1:
-      hipLaunchKernelGGL((k_leaf<K, V, 256, 4, RANK>), dim3(n_items), dim3(256), 0, s, items, b);
+      hipLaunchKernelGGL((k_leaf<K, V, 256, 4, RANK>), dim3(grid), dim3(256), 0, s, items, count, cap, b);
       break;
     case 2:
-      hipLaunchKernelGGL((k_leaf<K, V, 256, 16, RANK>), dim3(n_items), dim3(256), 0, s, items, b);
+      hipLaunchKernelGGL((k_leaf<K, V, 256, 16, RANK>), dim3(grid), dim3(256), 0, s, items, count, cap, b);
       break;
     case 3:
-      hipLaunchKernelGGL((k_leaf<K, V, 512, 16, RANK>), dim3(n_items), dim3(512), 0, s, items, b);
+      hipLaunchKernelGGL((k_leaf<K, V, 512, 16, RANK>), dim3(grid), dim3(512), 0, s, items, count, cap, b);
       break;
     default:
       if constexpr (big8) {
-        hipLaunchKernelGGL((k_leaf<K, V, 512, 16, RANK>), dim3(n_items), dim3(512), 0, s, items, b);
+        hipLaunchKernelGGL((k_leaf<K, V, 512, 16, RANK>), dim3(grid), dim3(512), 0, s, items, count, cap, b);
       } else {
-        hipLaunchKernelGGL((k_leaf<K, V, 1024, 16, RANK>), dim3(n_items), dim3(1024), 0, s, items, b);
+        hipLaunchKernelGGL((k_leaf<K, V, 1024, 16, RANK>), dim3(grid), dim3(1024), 0, s, items, count, cap, b);
       }
   }
 }
 
 template <typename K, typename V>
-void launch_leaf(const Leaf* items, uint32_t n_items, int cls, Bufs<K, V> b, hipStream_t s) {
-  if (n_items == 0) return;
+void launch_leaf(const Leaf* items, const uint32_t* count, uint32_t cap, uint32_t grid, int cls, Bufs<K, V> b,
+                 hipStream_t s) {
+  if (grid == 0 || cap == 0) return;
   const int m = leaf_rank_mode();
   if (m == RANK_BALLOT)
-    launch_leaf_r<K, V, RANK_BALLOT>(items, n_items, cls, b, s);
+    launch_leaf_r<K, V, RANK_BALLOT>(items, count, cap, grid, cls, b, s);
   else if (m == RANK_HYBRID)
-    launch_leaf_r<K, V, RANK_HYBRID>(items, n_items, cls, b, s);
+    launch_leaf_r<K, V, RANK_HYBRID>(items, count, cap, grid, cls, b, s);
   else if (m == RANK_PIPE)
-    launch_leaf_r<K, V, RANK_PIPE>(items, n_items, cls, b, s);
+    launch_leaf_r<K, V, RANK_PIPE>(items, count, cap, grid, cls, b, s);
   else
-    launch_leaf_r<K, V, RANK_LDS>(items, n_items, cls, b, s);
+    launch_leaf_r<K, V, RANK_LDS>(items, count, cap, grid, cls, b, s);
 }
 
 template void launch_plan<uint32_t>(const LevelArgs&, const uint32_t*, const uint32_t*, hipStream_t);
 template void launch_plan<uint64_t>(const LevelArgs&, const uint64_t*, const uint64_t*, hipStream_t);
-#define DTS_INST(K, V) template void launch_leaf<K, V>(const Leaf*, uint32_t, int, Bufs<K, V>, hipStream_t);
+#define DTS_INST(K, V) \
+  template void launch_leaf<K, V>(const Leaf*, const uint32_t*, uint32_t, uint32_t, int, Bufs<K, V>, hipStream_t);
 DTS_INST(uint32_t, NoVal)
 DTS_INST(uint64_t, NoVal)
 DTS_INST(uint64_t, uint64_t)

@@ -232,8 +232,10 @@ __global__ __launch_bounds__(256) void k_children(LevelArgs a) {
   constexpr int ZPT = (1 << GMAX) / 256;
   constexpr bool HV = HasVal<V>::value;
   __shared__ Reserve r;
-  const Task t = a.tasks[blockIdx.x];
-  if (t.n_chunks == 0) return;
+  const uint32_t n_tasks = a.ctr->cur_tasks;
+  for (uint32_t ti = blockIdx.x; ti < n_tasks; ti += gridDim.x) {
+  const Task t = a.tasks[ti];
+  if (t.n_chunks == 0) continue;
   reserve_init(&r);
   __syncthreads();
   const bool learned = (t.flags & TF_LEARNED) != 0;
@@ -347,43 +349,53 @@ __global__ __launch_bounds__(256) void k_children(LevelArgs a) {
     }
     a.merges[mi] = g;
   }
+  __syncthreads();
+  }
 }
 
 template <typename K, typename V>
 void launch_children(const LevelArgs& a, Bufs<K, V> b, hipStream_t s) {
   (void)b;
-  hipLaunchKernelGGL((k_children<K, V>), dim3(a.n_tasks), dim3(256), 0, s, a);
+  hipLaunchKernelGGL((k_children<K, V>), dim3(a.grid_tasks), dim3(256), 0, s, a);
 }
 
 // ------------------------------------------------------------------ copies
 template <typename K, typename V>
-__global__ __launch_bounds__(256) void k_copy(const Leaf* items, Bufs<K, V> bf) {
-  const Leaf it = items[blockIdx.x];
-  const K* ki = bf.k[it.from] + it.off;
-  K* ko = bf.k[it.to] + it.off;
-  for (uint32_t i = threadIdx.x; i < it.size; i += 256) ko[i] = ki[i];
-  if constexpr (HasVal<V>::value) {
-    const V* vi = bf.v[it.from] + it.off;
-    V* vo = bf.v[it.to] + it.off;
-    for (uint32_t i = threadIdx.x; i < it.size; i += 256) vo[i] = vi[i];
+__global__ __launch_bounds__(256) void k_copy(const Leaf* items, const uint32_t* count, uint32_t cap, Bufs<K, V> bf) {
+  const uint32_t n_items = min(*count, cap);
+  for (uint32_t ci = blockIdx.x; ci < n_items; ci += gridDim.x) {
+    const Leaf it = items[ci];
+    const K* ki = bf.k[it.from] + it.off;
+    K* ko = bf.k[it.to] + it.off;
+    for (uint32_t i = threadIdx.x; i < it.size; i += 256) ko[i] = ki[i];
+    if constexpr (HasVal<V>::value) {
+      const V* vi = bf.v[it.from] + it.off;
+      V* vo = bf.v[it.to] + it.off;
+      for (uint32_t i = threadIdx.x; i < it.size; i += 256) vo[i] = vi[i];
+    }
   }
 }
 
 template <typename K, typename V>
-void launch_copy(const Leaf* items, uint32_t n_items, Bufs<K, V> b, hipStream_t s) {
-  if (n_items == 0) return;
-  hipLaunchKernelGGL((k_copy<K, V>), dim3(n_items), dim3(256), 0, s, items, b);
+void launch_copy(const Leaf* items, const uint32_t* count, uint32_t cap, uint32_t grid, Bufs<K, V> b, hipStream_t s) {
+  if (grid == 0 || cap == 0) return;
+  hipLaunchKernelGGL((k_copy<K, V>), dim3(grid), dim3(256), 0, s, items, count, cap, b);
 }
 
 // ------------------------------------------------------------------ merges
-__global__ __launch_bounds__(64) void k_merge_units(const Merge* m, uint2* munits) {
-  const Merge mg = m[blockIdx.x];
-  for (uint32_t j = threadIdx.x; j < mg.n_units; j += 64) munits[mg.unit_base + j] = make_uint2(blockIdx.x, j);
+__global__ __launch_bounds__(64) void k_merge_units(const Merge* m, const uint32_t* count, uint32_t cap,
+                                                     uint2* munits) {
+  const uint32_t n_merges = min(*count, cap);
+  for (uint32_t mi = blockIdx.x; mi < n_merges; mi += gridDim.x) {
+    const Merge mg = m[mi];
+    for (uint32_t j = threadIdx.x; j < mg.n_units; j += 64) munits[mg.unit_base + j] = make_uint2(mi, j);
+  }
 }
 
-void launch_merge_units(const Merge* m, uint32_t n_merges, uint2* munits, hipStream_t s) {
-  if (n_merges == 0) return;
-  hipLaunchKernelGGL(k_merge_units, dim3(n_merges), dim3(64), 0, s, m, munits);
+void launch_merge_units(const Merge* m, const uint32_t* count, uint32_t cap, uint32_t grid, uint2* munits,
+                        hipStream_t s) {
+  if (grid == 0 || cap == 0) return;
+  hipLaunchKernelGGL(k_merge_units, dim3(grid), dim3(64), 0, s, m, count, cap, munits);
 }
 
 // Alg. 3, first line: p_i = lower_bound(B0, h_i) + sum_{j<i} |B_j| for every
@@ -391,8 +403,11 @@ void launch_merge_units(const Merge* m, uint32_t n_merges, uint2* munits, hipStr
 // is stored in the slot's light-id area (free once the level's children are
 // planned), at the heavy key's index.
 template <typename K>
-__global__ __launch_bounds__(64) void k_merge_pos(const Merge* m, uint8_t* tab, const K* k0, const K* k1) {
-  const Merge mg = m[blockIdx.x];
+__global__ __launch_bounds__(64) void k_merge_pos(const Merge* m, const uint32_t* count, uint32_t cap, uint8_t* tab,
+                                                   const K* k0, const K* k1) {
+  const uint32_t n_merges = min(*count, cap);
+  for (uint32_t mi = blockIdx.x; mi < n_merges; mi += gridDim.x) {
+  const Merge mg = m[mi];
   const SlotLayout sl = slot_layout(mg.g, false);
   uint8_t* slot = tab + mg.tab_off;
   uint32_t* P = (uint32_t*)(slot + sl.light);
@@ -429,18 +444,21 @@ __global__ __launch_bounds__(64) void k_merge_pos(const Merge* m, uint8_t* tab, 
     if (i < mg.m) P[mg.hbase + i] = lb + carry + x - sz;
     carry += __shfl(x, 63, 64);
   }
+  }
 }
 
 // Out-of-place gather of a zone: output q takes heavy bucket i when
 // p_i <= q < p_i + |B_i|, else light record q - (heavy records before q).
 template <typename K, typename V>
-__global__ __launch_bounds__(256) void k_merge_gather(const Merge* m, const uint2* munits, uint8_t* tab,
-                                                      Bufs<K, V> bf) {
+__global__ __launch_bounds__(256) void k_merge_gather(const Merge* m, const uint2* munits, const uint32_t* count,
+                                                      uint32_t cap, uint8_t* tab, Bufs<K, V> bf) {
   constexpr int MAXH = 1 << (GMAX - 1);
   __shared__ uint32_t P[MAXH], S[MAXH], PRE[MAXH];
   __shared__ K HK[MAXH];
   __shared__ uint32_t tmp[5];
-  const uint2 u = munits[blockIdx.x];
+  const uint32_t n_units = min(*count, cap);
+  for (uint32_t ui = blockIdx.x; ui < n_units; ui += gridDim.x) {
+  const uint2 u = munits[ui];
   const Merge mg = m[u.x];
   const SlotLayout sl = slot_layout(mg.g, false);
   const uint8_t* slot = tab + mg.tab_off;
@@ -500,23 +518,92 @@ __global__ __launch_bounds__(256) void k_merge_gather(const Merge* m, const uint
       }
     }
   }
+  __syncthreads();
+  }
 }
 
 template <typename K, typename V>
-void launch_merge(const Merge* m, uint32_t n_merges, const uint2* munits, uint32_t n_munits, uint8_t* tab,
-                  Bufs<K, V> b, hipStream_t s) {
-  if (n_merges == 0) return;
-  hipLaunchKernelGGL((k_merge_pos<K>), dim3(n_merges), dim3(64), 0, s, m, tab, (const K*)b.k[0],
-                     (const K*)b.k[1]);
-  hipLaunchKernelGGL((k_merge_gather<K, V>), dim3(n_munits), dim3(256), 0, s, m, munits, tab, b);
+void launch_merge(const Merge* m, const uint32_t* n_merges, uint32_t merge_cap, uint32_t merge_grid,
+                  const uint2* munits, const uint32_t* n_munits, uint32_t munit_cap, uint32_t munit_grid,
+                  uint8_t* tab, Bufs<K, V> b, hipStream_t s) {
+  if (merge_grid == 0 || merge_cap == 0) return;
+  hipLaunchKernelGGL((k_merge_pos<K>), dim3(merge_grid), dim3(64), 0, s, m, n_merges, merge_cap, tab,
+                     (const K*)b.k[0], (const K*)b.k[1]);
+  if (munit_grid == 0 || munit_cap == 0) return;
+  hipLaunchKernelGGL((k_merge_gather<K, V>), dim3(munit_grid), dim3(256), 0, s, m, munits, n_munits, munit_cap, tab,
+                     b);
 }
+
+// ------------------------------------------------------------------ roots
+template <typename K>
+__global__ void k_root(Task* tk, LevelCounters* in, uint64_t n, int key_bits, int gamma) {
+  uint32_t* cw = reinterpret_cast<uint32_t*>(in);
+  for (uint32_t i = threadIdx.x; i < sizeof(LevelCounters) / 4; i += blockDim.x) cw[i] = 0u;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    Task t;
+    t.off = 0;
+    t.cm_off = 0;
+    t.tab_off = 0;
+    t.size = (uint32_t)n;
+    t.n_root = (uint32_t)n;
+    t.level = 0;
+    t.unit_base = 0;
+    t.n_chunks = 0;
+    t.hi = (uint8_t)key_bits;
+    t.src = 0;
+    t.tgt = 0;
+    t.flags = 0;
+    t.gamma = (uint8_t)gamma;
+    t.w = 0;
+    t.shift = 0;
+    t.top = 0;
+    t.n_heavy = 0;
+    t.n_buckets = 0;
+    tk[0] = t;
+    in->next_tasks = 1;
+    in->next_records = (uint32_t)n;
+    in->next_max_size = (uint32_t)n;
+  }
+}
+
+template <typename K>
+void launch_root(Task* t, LevelCounters* in, uint64_t n, int key_bits, int gamma, hipStream_t s) {
+  hipLaunchKernelGGL(k_root<K>, dim3(1), dim3(64), 0, s, t, in, n, key_bits, gamma);
+}
+
+__global__ void k_zero_counters(LevelCounters* c, uint32_t words) {
+  uint32_t* w = reinterpret_cast<uint32_t*>(c);
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < words; i += gridDim.x * blockDim.x) w[i] = 0u;
+}
+
+void launch_zero_counters(LevelCounters* c, uint32_t n, hipStream_t s) {
+  const uint32_t words = n * (uint32_t)(sizeof(LevelCounters) / 4);
+  hipLaunchKernelGGL(k_zero_counters, dim3((words + 255) / 256), dim3(256), 0, s, c, words);
+}
+
+uint32_t persistent_grid(uint32_t wg_per_cu) {
+  static int cus = [] {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                                 hipSuccess || n <= 0) {
+      (void)hipGetLastError();
+      n = 256;
+    }
+    return n;
+  }();
+  return (uint32_t)cus * wg_per_cu;
+}
+
+template void launch_root<uint32_t>(Task*, LevelCounters*, uint64_t, int, int, hipStream_t);
+template void launch_root<uint64_t>(Task*, LevelCounters*, uint64_t, int, int, hipStream_t);
 
 #define DTS_INST(K, V)                                                                                      \
   template void launch_children<K, V>(const LevelArgs&, Bufs<K, V>, hipStream_t);                          \
   template void launch_seed_segments<K, V>(const LevelArgs&, const uint64_t*, uint32_t, uint64_t, hipStream_t); \
-  template void launch_copy<K, V>(const Leaf*, uint32_t, Bufs<K, V>, hipStream_t);                         \
-  template void launch_merge<K, V>(const Merge*, uint32_t, const uint2*, uint32_t, uint8_t*, Bufs<K, V>,   \
-                                   hipStream_t);
+  template void launch_copy<K, V>(const Leaf*, const uint32_t*, uint32_t, uint32_t, Bufs<K, V>, hipStream_t); \
+  template void launch_merge<K, V>(const Merge*, const uint32_t*, uint32_t, uint32_t, const uint2*,        \
+                                   const uint32_t*, uint32_t, uint32_t, uint8_t*, Bufs<K, V>, hipStream_t);
 DTS_INST(uint32_t, NoVal)
 DTS_INST(uint64_t, NoVal)
 DTS_INST(uint64_t, uint64_t)

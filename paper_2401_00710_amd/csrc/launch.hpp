@@ -7,10 +7,17 @@ namespace dts {
 constexpr int LEAF_CLASSES_MAX = 6;
 
 // Per-level device state handed to the kernels of one recursion level.
+//
+// Work counts are read on the device: `in` holds the counters the previous
+// step wrote (next_tasks, next_records), and the prep step of the level
+// writes cur_tasks, chunk and cur_units into `ctr`.  Every kernel of the
+// level loops over its items with a grid stride, so the host may launch any
+// grid (the exact count after a read-back, or a fixed persistent grid when
+// the whole sort is recorded into a graph without read-backs).
 struct LevelArgs {
   Task* tasks;
-  uint32_t n_tasks;
-  uint32_t chunk;        // records per distribution unit (multiple of every tile size)
+  uint32_t n_tasks;      // capacity of `tasks` (the exact count when it is known on the host)
+  uint32_t chunk;        // records per distribution unit; 0: the prep step derives it from the level's records
   uint2* units;          // (task index, chunk index) per distribution unit
   uint8_t* tab;          // table arena of this level
   uint32_t slot_bytes;   // bytes per task slot
@@ -22,7 +29,8 @@ struct LevelArgs {
   Leaf* copies;
   Merge* merges;
   Leaf* spills;
-  LevelCounters* ctr;
+  const LevelCounters* in;  // counters of the step that created this level's tasks
+  LevelCounters* ctr;       // this level's counters (zeroed by the prep step)
   Caps caps;
   // configuration
   uint64_t seed;
@@ -31,7 +39,14 @@ struct LevelArgs {
   uint32_t leaf_max[LEAF_CLASSES_MAX];  // size limit of each leaf class
   int plain;
   int key_bits;
+  int tile;  // scatter tile shape (0..3, see launch_distribute)
+  uint32_t grid_tasks;  // launch grid of the per-task kernels
+  uint32_t grid_units;  // launch grid of the per-unit kernels
 };
+
+// Grid of the persistent (grid-stride) launches: workgroups per compute unit
+// times the compute units of the current device.
+uint32_t persistent_grid(uint32_t wg_per_cu);
 
 template <typename K>
 void launch_plan(const LevelArgs& a, const K* k0, const K* k1, hipStream_t s);
@@ -46,6 +61,14 @@ uint32_t dist_cols(int g_level_max);
 
 void launch_prep(const LevelArgs& a, hipStream_t s);
 
+// Root of a whole-array sort, written on the device: one task and the
+// counters a level reads (graph-recordable; no host staging).
+template <typename K>
+void launch_root(Task* t, LevelCounters* in, uint64_t n, int key_bits, int gamma, hipStream_t s);
+
+// Zeroes `n` counter blocks (a kernel, so that it can be recorded in a graph).
+void launch_zero_counters(LevelCounters* c, uint32_t n, hipStream_t s);
+
 template <typename K, typename V>
 void launch_children(const LevelArgs& a, Bufs<K, V> b, hipStream_t s);
 
@@ -53,17 +76,22 @@ template <typename K, typename V>
 void launch_seed_segments(const LevelArgs& a, const uint64_t* seg_off, uint32_t n_seg, uint64_t n_total,
                           hipStream_t s);
 
+// List kernels: `count` is the device-side number of items (the kernels loop
+// over min(*count, cap) items with a grid stride); `grid` is the launch grid.
 template <typename K, typename V>
-void launch_leaf(const Leaf* items, uint32_t n_items, int cls, Bufs<K, V> b, hipStream_t s);
+void launch_leaf(const Leaf* items, const uint32_t* count, uint32_t cap, uint32_t grid, int cls, Bufs<K, V> b,
+                 hipStream_t s);
 
 template <typename K, typename V>
-void launch_copy(const Leaf* items, uint32_t n_items, Bufs<K, V> b, hipStream_t s);
+void launch_copy(const Leaf* items, const uint32_t* count, uint32_t cap, uint32_t grid, Bufs<K, V> b, hipStream_t s);
 
-void launch_merge_units(const Merge* m, uint32_t n_merges, uint2* munits, hipStream_t s);
+void launch_merge_units(const Merge* m, const uint32_t* count, uint32_t cap, uint32_t grid, uint2* munits,
+                        hipStream_t s);
 
 template <typename K, typename V>
-void launch_merge(const Merge* m, uint32_t n_merges, const uint2* munits, uint32_t n_munits, uint8_t* tab,
-                  Bufs<K, V> b, hipStream_t s);
+void launch_merge(const Merge* m, const uint32_t* n_merges, uint32_t merge_cap, uint32_t merge_grid,
+                  const uint2* munits, const uint32_t* n_munits, uint32_t munit_cap, uint32_t munit_grid,
+                  uint8_t* tab, Bufs<K, V> b, hipStream_t s);
 
 // Learned partitioner (k_mlp.hip).
 int mlp_loss_grad(const float* p, const float* x, const float* y, uint32_t n, float* grad, float* loss, float* part,

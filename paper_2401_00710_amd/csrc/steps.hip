@@ -65,9 +65,18 @@ int plan_and_distribute(const K* keys, const V* vals, size_t n, int hi, int skip
   a.units = (uint2*)tmp.get(sizeof(uint2) * units);
   a.tab = (uint8_t*)tmp.get(sl.bytes);
   a.cm = (uint32_t*)tmp.get(4 * a.caps.cm);
-  a.ctr = (LevelCounters*)tmp.get(sizeof(LevelCounters));
-  if (!a.tasks || !a.units || !a.tab || !a.cm || !a.ctr) return DTSORT_ENOMEM;
-  SCHK(hipMemsetAsync(a.ctr, 0, sizeof(LevelCounters), s));
+  LevelCounters* ctr2 = (LevelCounters*)tmp.get(2 * sizeof(LevelCounters));
+  if (!a.tasks || !a.units || !a.tab || !a.cm || !ctr2) return DTSORT_ENOMEM;
+  a.in = ctr2;
+  a.ctr = ctr2 + 1;
+  a.grid_tasks = 1;
+  a.grid_units = (uint32_t)units;
+  LevelCounters root;
+  std::memset(&root, 0, sizeof(root));
+  root.next_tasks = 1;
+  root.next_records = (uint32_t)n;
+  root.next_max_size = (uint32_t)n;
+  SCHK(hipMemcpyAsync(ctr2, &root, sizeof(root), hipMemcpyHostToDevice, s));
   SCHK(hipMemsetAsync(a.tab, 0, sl.bytes, s));
   Task t;
   std::memset(&t, 0, sizeof(t));
@@ -150,12 +159,17 @@ int leaf_step(const K* keys, const V* vals, const uint64_t* seg, size_t n_seg, i
     b.v[0] = const_cast<V*>(vals);
     b.v[1] = out_v;
   }
+  uint32_t hcount[LEAF_CLASSES];
+  for (int c = 0; c < LEAF_CLASSES; ++c) hcount[c] = (uint32_t)cls[c].size();
+  uint32_t* dcount = (uint32_t*)tmp.get(sizeof(hcount));
+  if (!dcount) return DTSORT_ENOMEM;
+  SCHK(hipMemcpyAsync(dcount, hcount, sizeof(hcount), hipMemcpyHostToDevice, s));
   for (int c = 0; c < LEAF_CLASSES; ++c) {
     if (cls[c].empty()) continue;
     Leaf* d = (Leaf*)tmp.get(sizeof(Leaf) * cls[c].size());
     if (!d) return DTSORT_ENOMEM;
     SCHK(hipMemcpyAsync(d, cls[c].data(), sizeof(Leaf) * cls[c].size(), hipMemcpyHostToDevice, s));
-    launch_leaf<K, V>(d, (uint32_t)cls[c].size(), c, b, s);
+    launch_leaf<K, V>(d, dcount + c, hcount[c], hcount[c], c, b, s);
   }
   SCHK(hipGetLastError());
   SCHK(hipStreamSynchronize(s));
@@ -253,7 +267,10 @@ int dtsort_step_dtmerge_u64(const uint64_t* b0_keys, const uint64_t* b0_values, 
   Merge* dm = (Merge*)tmp.get(sizeof(Merge));
   const uint32_t nunits = (uint32_t)((zsize + 4095) / 4096);
   uint2* mu = (uint2*)tmp.get(sizeof(uint2) * nunits);
-  if (!zk || !tab || !dm || !mu || (hv && !zv)) return DTSORT_ENOMEM;
+  uint32_t* dcount = (uint32_t*)tmp.get(2 * sizeof(uint32_t));
+  if (!zk || !tab || !dm || !mu || !dcount || (hv && !zv)) return DTSORT_ENOMEM;
+  const uint32_t hcount[2] = {1u, nunits};
+  SCHK(hipMemcpyAsync(dcount, hcount, sizeof(hcount), hipMemcpyHostToDevice, s));
   if (b0) SCHK(hipMemcpyAsync(zk, b0_keys, 8 * b0, hipMemcpyDeviceToDevice, s));
   if (hv && b0) SCHK(hipMemcpyAsync(zv, b0_values, 8 * b0, hipMemcpyDeviceToDevice, s));
   if (hv && hs) SCHK(hipMemcpyAsync(zv + b0, heavy_values, 8 * hs, hipMemcpyDeviceToDevice, s));
@@ -283,19 +300,19 @@ int dtsort_step_dtmerge_u64(const uint64_t* b0_keys, const uint64_t* b0_values, 
   mg.out_buf = 1;
   mg.g = (uint8_t)g;
   SCHK(hipMemcpyAsync(dm, &mg, sizeof(mg), hipMemcpyHostToDevice, s));
-  launch_merge_units(dm, 1, mu, s);
+  launch_merge_units(dm, dcount, 1, 1, mu, s);
   if (hv) {
     Bufs<uint64_t, uint64_t> b;
     b.k[0] = zk;
     b.k[1] = out_keys;
     b.v[0] = zv;
     b.v[1] = out_values;
-    launch_merge<uint64_t, uint64_t>(dm, 1, mu, nunits, tab, b, s);
+    launch_merge<uint64_t, uint64_t>(dm, dcount, 1, 1, mu, dcount + 1, nunits, nunits, tab, b, s);
   } else {
     Bufs<uint64_t, NoVal> b;
     b.k[0] = zk;
     b.k[1] = out_keys;
-    launch_merge<uint64_t, NoVal>(dm, 1, mu, nunits, tab, b, s);
+    launch_merge<uint64_t, NoVal>(dm, dcount, 1, 1, mu, dcount + 1, nunits, nunits, tab, b, s);
   }
   SCHK(hipGetLastError());
   SCHK(hipStreamSynchronize(s));

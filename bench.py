@@ -221,8 +221,10 @@ def run_extra(dt, W, torch, np, n, args, opts, src_u32):
     keys, off = c["keys"].to(torch.int32), c["offsets"]
     total = keys.numel()
     kw = torch.empty_like(keys)
+    one("batched_4096_segments_graph", lambda: dt.sort_segmented(kw, off, opts=opts(graph=1)), keys, kw,
+        count=total, n_total=total, form="one HIP graph launch (device-driven levels, recorded once)")
     one("batched_4096_segments", lambda: dt.sort_segmented(kw, off, opts=opts()), keys, kw, count=total,
-        n_total=total)
+        n_total=total, form="one call, level loop with a host read-back per level")
     offh = off.cpu().tolist()
     o_plain = opts()
 
@@ -234,6 +236,8 @@ def run_extra(dt, W, torch, np, n, args, opts, src_u32):
     one("per_instance_calls_4096", per_instance, keys, kw, count=total)
     res["batched_speedup_vs_per_instance"] = round(res["per_instance_calls_4096"]["ms"] /
                                                    res["batched_4096_segments"]["ms"], 2)
+    res["batched_graph_speedup_vs_per_instance"] = round(res["per_instance_calls_4096"]["ms"] /
+                                                         res["batched_4096_segments_graph"]["ms"], 2)
     del keys, kw, off
     # learned partitioner vs sampling partitioner on the 64-bit mixture
     log("generating mixture u64")

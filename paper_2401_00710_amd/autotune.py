@@ -1,0 +1,160 @@
+"""Autotuner of libdtsort's launch parameters on the current GPU.
+
+For every record layout (32-bit keys, 64-bit keys, 64-bit pairs, the batched
+32-bit form) and size class it times whole sorts of seeded synthetic inputs
+through the C ABI and picks, by coordinate descent, the scatter tile shape,
+then the digit width, then the base-case cutoff.  The winners are written as
+rows of the text table the library reads when dtsort_opts.tuned = 1:
+
+    key_bytes val_bytes segmented log2n_lo log2n_hi digit_bits lds_cutoff tile_shape
+
+Usage (on a GPU):  python -m paper_2401_00710_amd.autotune --out tune_table.txt
+The output is only a speed choice: every parameter set sorts identically.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(HERE))
+
+TILES = (1, 2, 3, 4)
+DIGITS = (8, 9, 10)
+
+
+def _cutoffs(kb, vb):
+    return (4096, 8192) if (kb == 8 and vb) else (4096, 8192, 16384)
+
+
+def _inputs(torch, W, kb, vb, seg, n, dev):
+    """Half uniform, half Zipf-skewed keys (heavy duplicates), seeded."""
+    if seg:
+        c = W.make_config("segmented_u32", seed=0, device=dev)
+        return dict(keys=c["keys"].to(torch.int32), offsets=c["offsets"], vals=None)
+    half = n // 2
+    if kb == 4:
+        a = W.uniform_u32(half, seed=1, device=dev)
+        b = W.zipf_u32(n - half, 1.0, max(n - half, 2), seed=2, device=dev)
+        k = torch.cat([a, b]).to(torch.int32)
+    else:
+        a = W.uniform_u64(half, seed=1, device=dev)
+        b = W.zipf_u64(n - half, 1.0, max(n - half, 2), seed=2, device=dev)
+        k = torch.cat([a, b])
+    v = torch.arange(n, dtype=torch.int64, device=dev) if vb else None
+    return dict(keys=k, offsets=None, vals=v)
+
+
+def _time(dt, torch, case, inp, work, vwork, params, reps):
+    kb, vb, seg = case
+    o = dt.make_opts(**params)
+
+    def run():
+        if seg:
+            dt.sort_segmented(work, inp["offsets"], opts=o)
+        elif kb == 4:
+            dt.sort_u32(work, o)
+        elif vb:
+            dt.sort_pairs_u64(work, vwork, o)
+        else:
+            dt.sort_u64(work, o)
+
+    ts = []
+    for r in range(reps + 1):
+        work.copy_(inp["keys"])
+        if vwork is not None:
+            vwork.copy_(inp["vals"])
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        run()
+        e1.record()
+        torch.cuda.synchronize()
+        if r:
+            ts.append(e0.elapsed_time(e1))
+    return statistics.median(ts)
+
+
+def tune(sizes, reps, log):
+    import torch
+
+    import paper_2401_00710_amd as dt
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    rows, report = [], []
+    cases = [(4, 0, 0), (8, 0, 0), (8, 8, 0)]
+    # size classes: [lo, hi] of floor(log2 n) and the n timed for the class
+    classes = [(0, 21, sizes[0]), (22, 25, sizes[1]), (26, 63, sizes[2])]
+    plan = [(c, cl) for c in cases for cl in classes] + [((4, 0, 1), (0, 63, 0))]
+    for case, (lo, hi, n) in plan:
+        kb, vb, seg = case
+        inp = _inputs(torch, W, kb, vb, seg, n, dev)
+        work = torch.empty_like(inp["keys"])
+        vwork = torch.empty_like(inp["vals"]) if inp["vals"] is not None else None
+        best = dict(digit_bits=8, lds_cutoff=0, tile_shape=1)
+        if seg:
+            best["graph"] = 1
+        t_best = _time(dt, torch, case, inp, work, vwork, best, reps)
+        tried = {json.dumps(best, sort_keys=True): t_best}
+        for key, values in (("tile_shape", TILES), ("digit_bits", DIGITS), ("lds_cutoff", _cutoffs(kb, vb))):
+            for v in values:
+                p = dict(best)
+                p[key] = v
+                tag = json.dumps(p, sort_keys=True)
+                if tag in tried:
+                    continue
+                t = _time(dt, torch, case, inp, work, vwork, p, reps)
+                tried[tag] = t
+                log(f"  {case} n={inp['keys'].numel()} {p} {t:.3f} ms")
+                if t < t_best:
+                    best, t_best = p, t
+        log(f"{case} log2n [{lo},{hi}] best {best} {t_best:.3f} ms")
+        rows.append((kb, vb, seg, lo, hi, best["digit_bits"], best["lds_cutoff"], best["tile_shape"]))
+        report.append(dict(case=case, n=int(inp["keys"].numel()), best=best, ms=t_best,
+                           tried={k: round(v, 4) for k, v in tried.items()}))
+        del inp, work, vwork
+        torch.cuda.empty_cache()
+    return rows, report
+
+
+def write_table(rows, path, device_name):
+    with open(path, "w") as f:
+        f.write("# Tuning table of libdtsort (read when dtsort_opts.tuned = 1).\n")
+        f.write("# Columns: key_bytes val_bytes segmented log2n_lo log2n_hi digit_bits lds_cutoff tile_shape\n")
+        f.write("# (0 = automatic).  First matching row wins.\n")
+        f.write(f"# Written by python -m paper_2401_00710_amd.autotune on {device_name}, "
+                f"{time.strftime('%Y-%m-%d')}.\n")
+        for r in rows:
+            f.write(" ".join(str(x) for x in r) + "\n")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=os.path.join(HERE, "tune_table.txt"))
+    ap.add_argument("--report", default=None, help="JSON file with every timing")
+    ap.add_argument("--sizes", default="1048576,16777216,268435456",
+                    help="n timed for the classes log2n <= 21, 22..25, >= 26")
+    ap.add_argument("--reps", type=int, default=2)
+    args = ap.parse_args()
+    import torch
+
+    def log(m):
+        print(m, flush=True)
+
+    sizes = [int(x) for x in args.sizes.split(",")]
+    rows, report = tune(sizes, args.reps, log)
+    write_table(rows, args.out, torch.cuda.get_device_name(0))
+    if args.report:
+        with open(args.report, "w") as f:
+            json.dump(report, f, indent=1)
+    log(f"wrote {args.out}")
+
+
+if __name__ == "__main__":
+    main()

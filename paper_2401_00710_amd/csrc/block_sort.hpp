@@ -16,9 +16,30 @@
 
 namespace dts {
 
+// A "block" of THREADS = 64 is one wave of a possibly larger workgroup (the
+// waves of such a workgroup sort independently): its thread index is the
+// lane and it synchronises with a wave barrier; larger blocks are the whole
+// workgroup.
+template <int THREADS>
+__device__ inline int btid() {
+  return THREADS == WAVE ? (int)(threadIdx.x & (WAVE - 1)) : (int)threadIdx.x;
+}
+
+template <int THREADS>
+__device__ inline void bsync() {
+  if constexpr (THREADS == WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
 template <int THREADS, int ITEMS>
 __device__ inline int striped_index(int i) {
-  return (threadIdx.x / WAVE) * WAVE * ITEMS + i * WAVE + (threadIdx.x & (WAVE - 1));
+  const int t = btid<THREADS>();
+  return (t / WAVE) * WAVE * ITEMS + i * WAVE + (t & (WAVE - 1));
 }
 
 // LDS words (u32) needed for the counters of block_radix_sort.
@@ -45,16 +66,16 @@ __device__ void block_radix_sort(K (&k)[ITEMS], uint16_t (&ix)[ITEMS], int lo_bi
                                  int n = THREADS * ITEMS) {
   constexpr int WAVES = THREADS / WAVE;
   constexpr int DPT = (256 + THREADS - 1) / THREADS;  // digits per thread in the scan
-  const int wv = threadIdx.x / WAVE;
-  const int lane = threadIdx.x & (WAVE - 1);
+  const int wv = btid<THREADS>() / WAVE;
+  const int lane = btid<THREADS>() & (WAVE - 1);
   uint32_t* tmp = cnt + WAVES * 256;
   unsigned long long* wm = mk + (RANK != RANK_BALLOT ? wv * 256 : 0);
   const int row0 = wv * WAVE * ITEMS;  // first element of this wave
   for (int bit = lo_bit; bit < hi_bit; bit += 8) {
     const int nbits = min(8, hi_bit - bit);
     const uint32_t dmask = (1u << nbits) - 1u;
-    for (int i = threadIdx.x; i < WAVES * 256; i += THREADS) cnt[i] = 0;
-    __syncthreads();
+    for (int i = btid<THREADS>(); i < WAVES * 256; i += THREADS) cnt[i] = 0;
+    bsync<THREADS>();
     uint32_t* wc = cnt + wv * 256;
     uint32_t pos[ITEMS];
     if constexpr (RANK == RANK_PIPE) {
@@ -89,13 +110,13 @@ __device__ void block_radix_sort(K (&k)[ITEMS], uint16_t (&ix)[ITEMS], int lo_bi
         if (r == 0) wc[d] = base + c;
       }
     }
-    __syncthreads();
+    bsync<THREADS>();
     // exclusive offsets in (digit, wave) order; thread t owns digits [t*DPT, t*DPT+DPT)
     uint32_t sd[DPT];
     uint32_t S = 0;
 #pragma unroll
     for (int j = 0; j < DPT; ++j) {
-      const int d = threadIdx.x * DPT + j;
+      const int d = btid<THREADS>() * DPT + j;
       uint32_t x = 0;
       if (d < 256) {
         for (int w = 0; w < WAVES; ++w) x += cnt[w * 256 + d];
@@ -107,7 +128,7 @@ __device__ void block_radix_sort(K (&k)[ITEMS], uint16_t (&ix)[ITEMS], int lo_bi
     uint32_t run = block_excl_scan<THREADS>(S, tmp, &total);
 #pragma unroll
     for (int j = 0; j < DPT; ++j) {
-      const int d = threadIdx.x * DPT + j;
+      const int d = btid<THREADS>() * DPT + j;
       if (d < 256) {
         uint32_t r2 = run;
         for (int w = 0; w < WAVES; ++w) {
@@ -118,7 +139,7 @@ __device__ void block_radix_sort(K (&k)[ITEMS], uint16_t (&ix)[ITEMS], int lo_bi
       }
       run += sd[j];
     }
-    __syncthreads();
+    bsync<THREADS>();
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
       if (row0 + i * WAVE + lane < n) {
@@ -128,7 +149,7 @@ __device__ void block_radix_sort(K (&k)[ITEMS], uint16_t (&ix)[ITEMS], int lo_bi
         if constexpr (IDX) si[p] = ix[i];
       }
     }
-    __syncthreads();
+    bsync<THREADS>();
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
       const int e = striped_index<THREADS, ITEMS>(i);
@@ -137,7 +158,7 @@ __device__ void block_radix_sort(K (&k)[ITEMS], uint16_t (&ix)[ITEMS], int lo_bi
         if constexpr (IDX) ix[i] = si[e];
       }
     }
-    __syncthreads();
+    bsync<THREADS>();
   }
 }
 
@@ -159,12 +180,12 @@ __device__ inline void block_or_and(const K (&k)[ITEMS], int n, K* red, K* out_o
     o |= __shfl_xor(o, off, WAVE);
     a &= __shfl_xor(a, off, WAVE);
   }
-  const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+  const int lane = btid<THREADS>() & (WAVE - 1), wv = btid<THREADS>() / WAVE;
   if (lane == 0) {
     red[wv] = o;
     red[WAVES + wv] = a;
   }
-  __syncthreads();
+  bsync<THREADS>();
   K ro = 0, ra = ~(K)0;
   for (int w = 0; w < WAVES; ++w) {
     ro |= red[w];
@@ -172,7 +193,7 @@ __device__ inline void block_or_and(const K (&k)[ITEMS], int n, K* red, K* out_o
   }
   *out_or = ro;
   *out_and = ra;
-  __syncthreads();
+  bsync<THREADS>();
 }
 
 template <typename K>

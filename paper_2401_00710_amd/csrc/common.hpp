@@ -279,29 +279,36 @@ __device__ inline void rank_pipelined(const uint32_t (&v)[ITEMS], const bool (&v
 template <int THREADS>
 __device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t* tmp, uint32_t* total) {
   constexpr int WAVES = THREADS / WAVE;
-  const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+  const int lane = threadIdx.x & (WAVE - 1);
   uint32_t x = v;
 #pragma unroll
   for (int o = 1; o < WAVE; o <<= 1) {
     uint32_t y = __shfl_up(x, o, WAVE);
     if (lane >= o) x += y;
   }
-  if (lane == WAVE - 1) tmp[wv] = x;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t s = 0;
-    for (int w = 0; w < WAVES; ++w) {
-      uint32_t t = tmp[w];
-      tmp[w] = s;
-      s += t;
+  if constexpr (WAVES == 1) {
+    // a one-wave block (possibly one of several waves of the workgroup)
+    *total = __shfl(x, WAVE - 1, WAVE);
+    return x - v;
+  } else {
+    const int wv = threadIdx.x / WAVE;
+    if (lane == WAVE - 1) tmp[wv] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t s = 0;
+      for (int w = 0; w < WAVES; ++w) {
+        uint32_t t = tmp[w];
+        tmp[w] = s;
+        s += t;
+      }
+      tmp[WAVES] = s;
     }
-    tmp[WAVES] = s;
+    __syncthreads();
+    uint32_t r = x - v + tmp[wv];
+    *total = tmp[WAVES];
+    __syncthreads();
+    return r;
   }
-  __syncthreads();
-  uint32_t r = x - v + tmp[wv];
-  *total = tmp[WAVES];
-  __syncthreads();
-  return r;
 }
 
 // In-place exclusive scan of arr[0..n) in LDS by the whole workgroup; returns the total.

@@ -566,7 +566,7 @@ static int run_sort(Ctx* c, SortJob<K, V>& J, hipStream_t s, dtsort_stats* stats
     a.grid_units = (uint32_t)units;
     launch_prep(a, s);
     prof.begin(PK_PLAN);
-    launch_plan<K>(a, J.bufs.k[0], J.bufs.k[1], s);
+    launch_plan<K>(a, J.bufs.k[0], J.bufs.k[1], gmax, s);
     prof.end(0.0);
     if (learn_here) {
       HIPCHK(hipEventCreate(&le0));
@@ -654,7 +654,7 @@ struct GPlan {
   uint64_t tab_bytes = 0;
   uint32_t slot_bytes = 0;
   uint32_t grid_tasks = 0, grid_units = 0, grid_leaf[LEAF_CLASSES] = {}, grid_copy = 0, grid_mpos = 0,
-           grid_munit = 0, grid_spill = 0;
+           grid_munit = 0, grid_spill = 0, grid_finish = 0;
 };
 
 template <typename K, typename V>
@@ -663,11 +663,19 @@ static GPlan graph_plan(const SortJob<K, V>& J, const Params& P) {
   const uint64_t n = std::max<uint64_t>(J.n, 2);
   g.gmax = plan_gamma((uint32_t)std::min<uint64_t>(n, 0xFFFFFFFFu), P.gover);
   g.cutoff = P.cutoff;
-  // Each light child consumes at least one digit of the smallest width and an
-  // overflow child is followed by a level that does, so two levels remove at
-  // least gmin bits; one more level covers the last-digit step.
+  // Level bound: a task whose keys differ in at most gmin bits is the last of
+  // its branch (one plain digit).  Otherwise its light children have at least
+  // gmin fewer bits left, and its overflow child keeps the bits but takes the
+  // top digit with no leading-zero skip and has no overflow child itself, so
+  // its children have gmin fewer bits: two levels per digit, plus the last.
+  // The graph records the levels a branch needs when no overflow bucket
+  // occurs (one per digit); tasks still open after them (only below
+  // overflow buckets, which hold the few keys above a sample's maximum) are
+  // finished by one workgroup each.  DTSORT_GRAPH_LEVELS overrides the count.
   const int gmin = P.gover > 0 ? std::max(1, std::min(P.gover, GMAX)) : 8;
-  g.levels = std::min(MAX_LEVELS, 2 * ((J.key_bits + gmin - 1) / gmin) + 2);
+  const int kb = J.key_bits;
+  g.levels = std::min(MAX_LEVELS, kb <= gmin ? 1 : (kb - gmin + gmin - 1) / gmin + 1);
+  if (const char* e = getenv("DTSORT_GRAPH_LEVELS")) g.levels = std::max(1, std::min(MAX_LEVELS, atoi(e)));
   const uint64_t nbc = (uint64_t)nb_cap(g.gmax);
   const uint64_t tasks = n / (g.cutoff + 1ull) + 1;
   Caps& c = g.caps;
@@ -686,12 +694,15 @@ static GPlan graph_plan(const SortJob<K, V>& J, const Params& P) {
   auto pg = [](uint32_t per_cu, uint64_t cap) { return (uint32_t)std::min<uint64_t>(persistent_grid(per_cu), cap); };
   g.grid_tasks = pg(4, c.tasks);
   g.grid_units = pg(8, c.units);
+  // sorters per compute unit by leaf class (class 0 packs four one-wave
+  // sorters in a workgroup)
   const uint32_t per_cu[LEAF_CLASSES] = {16, 8, 4, 2, 2};
   for (int k = 0; k < LEAF_CLASSES; ++k) g.grid_leaf[k] = pg(per_cu[k], c.leaf);
   g.grid_copy = pg(4, c.copies);
   g.grid_mpos = pg(8, c.merges);
   g.grid_munit = pg(4, c.munits);
   g.grid_spill = pg(4, c.spills);
+  g.grid_finish = pg(1, c.tasks);
   return g;
 }
 
@@ -763,7 +774,7 @@ static void graph_enqueue(Work& W, const GPlan& g, const SortJob<K, V>& J, const
     a.grid_tasks = g.grid_tasks;
     a.grid_units = g.grid_units;
     launch_prep(a, s);
-    launch_plan<K>(a, J.bufs.k[0], J.bufs.k[1], s);
+    launch_plan<K>(a, J.bufs.k[0], J.bufs.k[1], g.gmax, s);
     launch_distribute<K, V>(a, J.bufs, g.gmax, 0x7FFFFFFFu, s, -1);
     launch_children<K, V>(a, J.bufs, s);
     for (int k = 0; k < LEAF_CLASSES; ++k)
@@ -771,6 +782,9 @@ static void graph_enqueue(Work& W, const GPlan& g, const SortJob<K, V>& J, const
     launch_copy<K, V>((Leaf*)W.copies.p, &a.ctr->copies, g.caps.copies, g.grid_copy, J.bufs, s);
     launch_merge_units((Merge*)K_.merges.p, &a.ctr->merges, g.caps.merges, g.grid_mpos, (uint2*)K_.munits.p, s);
   }
+  // tasks created by the last recorded level
+  launch_finish<K, V>((const Task*)W.tasks[g.levels & 1].p, &dctr[g.levels].next_tasks, g.caps.tasks, g.grid_finish,
+                      J.bufs, s);
   for (int L = g.levels - 1; L >= 0; --L) {
     LevelKeep& K_ = W.lv[L];
     LevelCounters* lc = dctr + L + 1;
@@ -787,12 +801,12 @@ struct GraphKey {
   const uint64_t* seg;
   uint32_t n_seg;
   uint64_t seed;
-  int key_bits, mode, gover, tile;
+  int key_bits, mode, gover, tile, levels;
   uint32_t cutoff;
   bool operator==(const GraphKey& o) const {
     return kb == o.kb && vb == o.vb && k == o.k && v == o.v && ws == o.ws && n == o.n && seg == o.seg &&
            n_seg == o.n_seg && seed == o.seed && key_bits == o.key_bits && mode == o.mode && gover == o.gover &&
-           tile == o.tile && cutoff == o.cutoff;
+           tile == o.tile && levels == o.levels && cutoff == o.cutoff;
   }
 };
 
@@ -802,6 +816,7 @@ struct GraphEntry {
   hipGraph_t g = nullptr;
   hipGraphExec_t x = nullptr;
   int levels = 0;
+  uint32_t levels_cap = 0;  // capacity of the task list the finishing step reads
   uint64_t used = 0;
 };
 
@@ -834,10 +849,11 @@ static int graph_sort(Ctx* c, SortJob<K, V>& J, void* user_ws, hipStream_t s, dt
   key.gover = P.gover;
   key.tile = P.tile;
   key.cutoff = P.cutoff;
+  const GPlan g = graph_plan(J, P);
+  key.levels = g.levels;
   GraphEntry* e = nullptr;
   for (GraphEntry* x : c->graphs)
     if (x->key == key) e = x;
-  const GPlan g = graph_plan(J, P);
   int r;
   if (!e) {
     if (c->graphs.size() >= MAX_GRAPHS) {
@@ -852,6 +868,7 @@ static int graph_sort(Ctx* c, SortJob<K, V>& J, void* user_ws, hipStream_t s, dt
     e = new GraphEntry();
     e->key = key;
     e->levels = g.levels;
+    e->levels_cap = g.caps.tasks;
     hipStream_t cs = c->cap_stream;
     if ((r = graph_alloc<K, V>(e->w, g, cs)) == 0 && !user_ws) {
       r = ensure(e->w.tk, dtsort_workspace_bytes((int)sizeof(K), HV ? (int)sizeof(V) : 0, J.n), cs);
@@ -894,7 +911,7 @@ static int graph_sort(Ctx* c, SortJob<K, V>& J, void* user_ws, hipStream_t s, dt
       err |= h[L].error;
       add_stats(stats, h[L], L > 0);
     }
-    if (h.back().next_tasks) err |= ERR_TASKS;  // work left after the last recorded level
+    if (h.back().next_tasks > e->levels_cap) err |= ERR_TASKS;  // more open tasks than the list holds
     if (err & ERR_SEGMENTS) return fail(DTSORT_EINVAL, "segment offsets are not valid");
     if (err) return fail(DTSORT_EINTERNAL, "device capacity check failed (flags " + std::to_string(err) + ")");
   }

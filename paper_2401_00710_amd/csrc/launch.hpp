@@ -48,8 +48,9 @@ struct LevelArgs {
 // times the compute units of the current device.
 uint32_t persistent_grid(uint32_t wg_per_cu);
 
+// g_level_max: the widest digit of the level's tasks (selects the sample capacity)
 template <typename K>
-void launch_plan(const LevelArgs& a, const K* k0, const K* k1, hipStream_t s);
+void launch_plan(const LevelArgs& a, const K* k0, const K* k1, int g_level_max, hipStream_t s);
 
 // phase 0: histogram; 1: column and bucket scans; 2: scatter; -1: all three
 template <typename K, typename V>
@@ -81,6 +82,12 @@ void launch_seed_segments(const LevelArgs& a, const uint64_t* seg_off, uint32_t 
 template <typename K, typename V>
 void launch_leaf(const Leaf* items, const uint32_t* count, uint32_t cap, uint32_t grid, int cls, Bufs<K, V> b,
                  hipStream_t s);
+
+// Tasks left after the last recorded level of the graph form: each sorted
+// completely by one workgroup.
+template <typename K, typename V>
+void launch_finish(const Task* tasks, const uint32_t* count, uint32_t cap, uint32_t grid, Bufs<K, V> b,
+                   hipStream_t s);
 
 template <typename K, typename V>
 void launch_copy(const Leaf* items, const uint32_t* count, uint32_t cap, uint32_t grid, Bufs<K, V> b, hipStream_t s);

@@ -87,7 +87,7 @@ int plan_and_distribute(const K* keys, const V* vals, size_t n, int hi, int skip
   t.gamma = (uint8_t)g;
   SCHK(hipMemcpyAsync(a.tasks, &t, sizeof(Task), hipMemcpyHostToDevice, s));
   launch_prep(a, s);
-  launch_plan<K>(a, keys, keys, s);
+  launch_plan<K>(a, keys, keys, g, s);
   if (distribute) {
     Bufs<K, V> b;
     b.k[0] = const_cast<K*>(keys);

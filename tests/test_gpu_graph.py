@@ -187,3 +187,46 @@ def test_tuned_table_path():
     dt.sort_u32(d, dt.make_opts(tuned=1))
     torch.cuda.synchronize()
     assert np.array_equal(host_u32(d), S.stable_sort_keys(k))
+
+
+@pytest.mark.parametrize("kind", ["uniform", "zipf", "bexp_pairs", "segmented"])
+def test_graph_finishing_step(kind, monkeypatch):
+    """With one recorded level and a small base-case cutoff, most buckets are
+    left to the finishing step (a whole-task LSD sort per workgroup); the
+    output must still be the oracle's."""
+    require_gpu()
+    say(f"graph finishing step {kind}")
+    monkeypatch.setenv("DTSORT_GRAPH_LEVELS", "1")
+    rs = np.random.default_rng(31)
+    n = 400_000
+    o = dt.make_opts(graph=1, lds_cutoff=300, seed=5)
+    if kind in ("uniform", "zipf"):
+        if kind == "uniform":
+            k = rs.integers(0, 2 ** 32, n, dtype=np.uint64).astype(np.uint32)
+        else:
+            k = (rs.zipf(1.3, n).astype(np.uint64) * np.uint64(0x9E3779B1) & np.uint64(0xFFFFFFFF)).astype(np.uint32)
+        d = dev_u32(k)
+        dt.sort_u32(d, o)
+        torch.cuda.synchronize()
+        assert np.array_equal(host_u32(d), S.stable_sort_keys(k))
+    elif kind == "bexp_pairs":
+        b = np.minimum(rs.geometric(0.1, n), 64)
+        low = rs.integers(0, 2 ** 63, n, dtype=np.uint64)
+        lead = np.left_shift(np.uint64(1), (b - 1).astype(np.uint64))
+        k = lead | (low & (lead - np.uint64(1)))
+        v = np.arange(n, dtype=np.uint64)
+        dk, dv = dev_u64(k), dev_u64(v)
+        dt.sort_pairs_u64(dk, dv, o)
+        torch.cuda.synchronize()
+        ek, ev = S.stable_sort_pairs(k, v)
+        assert np.array_equal(host_u64(dk), ek)
+        assert np.array_equal(host_u64(dv), ev)
+    else:
+        k, off = _segmented_case(3, n=n, n_seg=61)
+        v = np.arange(k.size, dtype=np.uint32)
+        dk, dv, do = dev_u32(k), dev_u32(v), dev_u64(off)
+        dt.sort_segmented(dk, do, dv, opts=o)
+        torch.cuda.synchronize()
+        ek, ev = S.segmented_sort(k, off, v)
+        assert np.array_equal(host_u32(dk), ek)
+        assert np.array_equal(host_u32(dv), ev)

@@ -103,7 +103,12 @@ def main():
     ap.add_argument("--digit-bits", type=int, default=-1, help="-1: autotuned table; 0: the paper's rule")
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1 << 26)
+    ap.add_argument("--once", default=None, metavar="WORKLOAD",
+                    help="for profilers: generate WORKLOAD, sort it once (tuned), print its time and exit; one of "
+                         + ", ".join(ONCE))
     args = ap.parse_args()
+    if args.once:
+        return run_once(args.once, int(args.n))
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU; --gpus above 1 is not supported "
                                    "(the sharded design is described in DESIGN.md)"}), flush=True)
@@ -182,6 +187,66 @@ def main():
         "extra": extra,
     }
     print(json.dumps(out), flush=True)
+
+
+ONCE = ("uniform_u32_1e9", "zipf1_u32_1e9", "exp_pairs_u64_1e9", "bexp_pairs_u64_1e9", "uniform_u64_1e9",
+        "mixture_u64_1e9", "mixture_u64_1e9_learned", "batched_4096_segments_graph", "batched_4096_segments")
+
+
+def run_once(name, n):
+    """One tuned sort of a named workload (input generated and restored outside
+    the sort), for kernel traces and counters; prints the sort's time."""
+    import torch
+
+    import paper_2401_00710_amd as dt
+    import workloads as W
+    if name not in ONCE:
+        raise SystemExit(f"unknown workload {name}; one of {', '.join(ONCE)}")
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    vals = vsrc = off = None
+    kw = {}
+    if name.startswith("batched"):
+        c = W.make_config("segmented_u32", seed=0, device=dev)
+        src, off = c["keys"].to(torch.int32), c["offsets"]
+        kw = dict(graph=1 if name.endswith("graph") else 0)
+    elif name.startswith("uniform_u32"):
+        src = W.uniform_u32(n, seed=0, device=dev).to(torch.int32)
+    elif name.startswith("zipf1_u32"):
+        src = W.zipf_u32(n, 1.0, n, seed=0, device=dev).to(torch.int32)
+    elif name.startswith("uniform_u64"):
+        src = W.uniform_u64(n, seed=0, device=dev)
+    elif name.startswith("mixture"):
+        src = W.mixture_u64(n, seed=0, device=dev)
+        if name.endswith("learned"):
+            kw = dict(mode=dt.MODE_LEARNED)
+    else:
+        src = (W.exponential_keys(n, 1e-5, seed=0, device=dev) if name.startswith("exp")
+               else W.bit_exponential_keys(n, 0.1, seed=0, device=dev))
+        vsrc = torch.arange(n, dtype=torch.int64, device=dev)
+        vals = torch.empty_like(vsrc)
+    work = torch.empty_like(src)
+    o = dt.make_opts(tuned=1, **kw)
+    times = []
+    for _ in range(2 if name.startswith("batched") else 1):  # a graph is recorded on its first call
+        work.copy_(src)
+        if vals is not None:
+            vals.copy_(vsrc)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        if off is not None:
+            dt.sort_segmented(work, off, opts=o)
+        elif vals is not None:
+            dt.sort_pairs_u64(work, vals, o)
+        elif src.element_size() == 4:
+            dt.sort_u32(work, o)
+        else:
+            dt.sort_u64(work, o)
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    print(json.dumps({"once": name, "ms": round(times[-1], 4)}), flush=True)
 
 
 def run_extra(dt, W, torch, np, n, args, opts, src_u32):

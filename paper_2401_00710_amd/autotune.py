@@ -23,7 +23,7 @@ import time
 HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(HERE))
 
-TILES = (1, 2, 3, 4)
+TILES = (1, 2, 3, 4, 5)
 DIGITS = (8, 9, 10)
 
 

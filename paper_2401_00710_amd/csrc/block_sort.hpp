@@ -162,6 +162,102 @@ __device__ void block_radix_sort(K (&k)[ITEMS], uint16_t (&ix)[ITEMS], int lo_bi
   }
 }
 
+// Stable sort by key bits [lo_bit, hi_bit) for wide bit ranges (more than
+// PREFIX_BITS + 8 bits): radix passes over the top PREFIX_BITS bits only,
+// then every run of equal prefix that
+// holds a descent is finished by a stable insertion sort (one thread per
+// run).  Keys whose prefixes are nearly unique need two passes instead of one
+// per 8 bits; runs of equal keys hold no descent.  If a run with a descent
+// is longer than FIX_MAX, the remaining passes run instead (low bits, then
+// the prefix again: a plain LSD sort, stable for the original order).  Same
+// arguments and results as block_radix_sort; `flag` is one LDS word, and cnt
+// doubles as the bitmap of runs to fix.
+constexpr int PREFIX_BITS = 16;
+constexpr int FIX_MAX = 32;
+
+template <typename K, int THREADS, int ITEMS, bool IDX, int RANK = RANK_BALLOT>
+__device__ void block_sort_bits(K (&k)[ITEMS], uint16_t (&ix)[ITEMS], int lo_bit, int hi_bit, K* sk, uint16_t* si,
+                                uint32_t* cnt, unsigned long long* mk, int n, uint32_t* flag) {
+  static_assert(THREADS * ITEMS / 32 <= bsort_cnt_words<THREADS>(), "run bitmap must fit in the counters");
+  if (hi_bit - lo_bit <= PREFIX_BITS + 8) {
+    // at most three passes: the prefix path would save at most one
+    block_radix_sort<K, THREADS, ITEMS, IDX, RANK>(k, ix, lo_bit, hi_bit, sk, si, cnt, mk, n);
+    return;
+  }
+  const int pb = hi_bit - PREFIX_BITS;
+  // rounds of radix passes (one call site for all of them):
+  // 0: [pb, hi); if the fix-up gives way, 1: [lo, pb) and 2: [pb, hi)
+  int r_lo = pb, r_hi = hi_bit;
+  for (int round = 0;; ++round) {
+    block_radix_sort<K, THREADS, ITEMS, IDX, RANK>(k, ix, r_lo, r_hi, sk, si, cnt, mk, n);
+    if (round != 0) {
+      if (round == 1) {
+        r_lo = pb;
+        r_hi = hi_bit;
+        continue;
+      }
+      return;
+    }
+    // sk (si) now hold the records in prefix order
+    const int t = btid<THREADS>();
+    uint32_t* bm = cnt;  // bit s: the run starting at s holds a descent
+    for (int w = t; w < (n + 31) / 32; w += THREADS) bm[w] = 0u;
+    if (t == 0) *flag = 0;
+    bsync<THREADS>();
+    auto pre = [&](K x) { return shr<K>(x, pb); };
+    for (int p = t + 1; p < n; p += THREADS) {
+      const K pr = pre(sk[p]);
+      if (pre(sk[p - 1]) != pr || !(sk[p - 1] > sk[p])) continue;  // no descent at p
+      int s0 = p - 1;
+      while (s0 > 0 && pre(sk[s0 - 1]) == pr && p - s0 < FIX_MAX) --s0;
+      int e = p + 1;
+      while (e < n && pre(sk[e]) == pr && e - s0 < FIX_MAX) ++e;
+      if ((s0 > 0 && pre(sk[s0 - 1]) == pr) || (e < n && pre(sk[e]) == pr)) {
+        atomicOr(flag, 1u);  // a run longer than FIX_MAX with a descent
+      } else {
+        atomicOr(&bm[s0 >> 5], 1u << (s0 & 31));
+      }
+    }
+    bsync<THREADS>();
+    if (*flag) {
+      r_lo = lo_bit;
+      r_hi = pb;
+      continue;
+    }
+    for (int p = t; p < n; p += THREADS) {
+      if (!((bm[p >> 5] >> (p & 31)) & 1u)) continue;
+      const K pr = pre(sk[p]);
+      int e = p + 1;
+      while (e < n && pre(sk[e]) == pr) ++e;  // at most FIX_MAX
+      // stable insertion sort of sk[p, e) (with si)
+      for (int j = p + 1; j < e; ++j) {
+        const K x = sk[j];
+        uint16_t xi = 0;
+        if constexpr (IDX) xi = si[j];
+        int i = j - 1;
+        while (i >= p && sk[i] > x) {
+          sk[i + 1] = sk[i];
+          if constexpr (IDX) si[i + 1] = si[i];
+          --i;
+        }
+        sk[i + 1] = x;
+        if constexpr (IDX) si[i + 1] = xi;
+      }
+    }
+    bsync<THREADS>();
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+      const int e = striped_index<THREADS, ITEMS>(i);
+      if (e < n) {
+        k[i] = sk[e];
+        if constexpr (IDX) ix[i] = si[e];
+      }
+    }
+    bsync<THREADS>();
+    return;
+  }
+}
+
 // Bitwise OR and AND of the first n elements held in k[] (striped layout),
 // reduced over the workgroup.  red: LDS of 2*(THREADS/64) K.
 template <typename K, int THREADS, int ITEMS>

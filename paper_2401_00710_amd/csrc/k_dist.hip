@@ -282,7 +282,8 @@ __global__ __launch_bounds__(256) void k_bucketscan(LevelArgs a) {
 //     its next free place in the bucket (global offset - tile start + index).
 // Equal buckets keep input order at every step: the scatter is stable.
 template <typename K, typename V, int T, int ITEMS, int NBMAX, int RANK>
-__global__ __launch_bounds__(T, (T == 512 && ITEMS <= 8 && ITEMS * sizeof(K) * (HasVal<V>::value ? 2 : 1) <= 64) ? 4 : 1) void k_scatter(LevelArgs a, Bufs<K, V> bf) {
+__global__ __launch_bounds__(T, ((T == 512 || T == 1024) && ITEMS <= 8 &&
+                                  ITEMS * sizeof(K) * (HasVal<V>::value ? 2 : 1) <= 64) ? 4 : 1) void k_scatter(LevelArgs a, Bufs<K, V> bf) {
   constexpr int WAVES = T / WAVE;
   constexpr int TILE = T * ITEMS;
   constexpr int PER = (NBMAX + T - 1) / T;  // buckets per thread in the bucket phase
@@ -504,7 +505,8 @@ uint32_t dist_cols(int) { return 1; }
 
 // Tile shapes of the scatter for digit widths <= 8 (LevelArgs::tile):
 // 0 = 512 threads x 16 keys (x 8 for 64-bit keys), 1 = 256 x 16, 2 = 512 x 8,
-// 3 = 256 x 32 (x 16).  Wider digits use 256 threads and 2048 counters.
+// 3 = 256 x 32 (x 16), 4 = 1024 x 8 (x 4).  Wider digits use 256 threads and
+// 2048 counters.
 template <typename K, typename V>
 void launch_distribute(const LevelArgs& a, Bufs<K, V> b, int g_level_max, uint32_t max_chunks, hipStream_t s,
                        int phase) {
@@ -522,6 +524,8 @@ void launch_distribute(const LevelArgs& a, Bufs<K, V> b, int g_level_max, uint32
       launch_dist_variant<K, V, NB8, 512, RANK_LDS, sizeof(K) == 4 ? 8 : 4>(a, b, max_chunks, s, phase);
     else if (a.tile == 3)
       launch_dist_variant<K, V, NB8, 256, RANK_LDS, sizeof(K) == 4 ? 32 : 16>(a, b, max_chunks, s, phase);
+    else if (a.tile == 4)
+      launch_dist_variant<K, V, NB8, 1024, RANK_LDS, sizeof(K) == 4 ? 8 : 4>(a, b, max_chunks, s, phase);
     else
       launch_dist_variant<K, V, NB8, 512, RANK_LDS>(a, b, max_chunks, s, phase);
   } else {

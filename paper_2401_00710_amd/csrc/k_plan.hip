@@ -34,6 +34,7 @@ __global__ __launch_bounds__(T, T == 512 ? 4 : 1) void k_plan(LevelArgs a, const
   __shared__ uint32_t hz[1 << (GMAX - 1)];
   __shared__ uint32_t tmp[T / WAVE + 1];
   __shared__ int s_top, s_w, s_shift;
+  __shared__ uint32_t s_flag;
 
   const uint32_t n_tasks = a.ctr->cur_tasks;
   for (uint32_t ti = blockIdx.x; ti < n_tasks; ti += gridDim.x) {
@@ -79,8 +80,8 @@ __global__ __launch_bounds__(T, T == 512 ? 4 : 1) void k_plan(LevelArgs a, const
     block_or_and<K, T, ITEMS>(kk, (int)ns, red, &vor, &vand);
     const K diff = (vor ^ vand) & mask_below<K>(hi);
     if (diff) {
-      block_radix_sort<K, T, ITEMS, false>(kk, dummy, trailing_zeros(diff), bit_length(diff), sk, nullptr, cnt,
-                                           nullptr, (int)ns);
+      block_sort_bits<K, T, ITEMS, false>(kk, dummy, trailing_zeros(diff), bit_length(diff), sk, nullptr, cnt,
+                                          nullptr, (int)ns, &s_flag);
     } else {
 #pragma unroll
       for (int i = 0; i < ITEMS; ++i) sk[striped_index<T, ITEMS>(i)] = kk[i];
@@ -180,6 +181,7 @@ __global__ __launch_bounds__(T* SUB) void k_leaf(const Leaf* items, const uint32
   __shared__ uint32_t cnt_all[SUB][bsort_cnt_words<T>()];
   __shared__ unsigned long long mk_all[SUB][USE_LDS ? bsort_match_words<T>() : 1];
   __shared__ K red_all[SUB][2 * (T / WAVE)];
+  __shared__ uint32_t flag_all[SUB];
   const int sub = SUB == 1 ? 0 : (int)(threadIdx.x / T);
   K* sk = sk_all[sub];
   uint16_t* si = si_all[sub];
@@ -207,7 +209,8 @@ __global__ __launch_bounds__(T* SUB) void k_leaf(const Leaf* items, const uint32
     block_or_and<K, T, ITEMS>(kk, n, red, &vor, &vand);
     const K diff = (vor ^ vand) & mask_below<K>(it.bits);
     if (diff) {
-      block_radix_sort<K, T, ITEMS, HV, RANK>(kk, ix, trailing_zeros(diff), bit_length(diff), sk, si, cnt, mk, n);
+      block_sort_bits<K, T, ITEMS, HV, RANK>(kk, ix, trailing_zeros(diff), bit_length(diff), sk, si, cnt, mk, n,
+                                             &flag_all[sub]);
     }
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
@@ -382,11 +385,15 @@ static void launch_leaf_r(const Leaf* items, const uint32_t* count, uint32_t cap
       hipLaunchKernelGGL((k_leaf<K, V, 256, 16, RANK>), dim3(grid), dim3(256), 0, s, items, count, cap, b);
       break;
     case 3:
-      hipLaunchKernelGGL((k_leaf<K, V, 512, 16, RANK>), dim3(grid), dim3(512), 0, s, items, count, cap, b);
+      if constexpr (sizeof(K) == 8) {  // 16 waves for 8-byte keys (registers allow it at 8 keys each)
+        hipLaunchKernelGGL((k_leaf<K, V, 1024, 8, RANK>), dim3(grid), dim3(1024), 0, s, items, count, cap, b);
+      } else {
+        hipLaunchKernelGGL((k_leaf<K, V, 512, 16, RANK>), dim3(grid), dim3(512), 0, s, items, count, cap, b);
+      }
       break;
     default:
       if constexpr (big8) {
-        hipLaunchKernelGGL((k_leaf<K, V, 512, 16, RANK>), dim3(grid), dim3(512), 0, s, items, count, cap, b);
+        hipLaunchKernelGGL((k_leaf<K, V, 1024, 8, RANK>), dim3(grid), dim3(1024), 0, s, items, count, cap, b);
       } else {
         hipLaunchKernelGGL((k_leaf<K, V, 1024, 16, RANK>), dim3(grid), dim3(1024), 0, s, items, count, cap, b);
       }

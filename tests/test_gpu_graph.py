@@ -158,7 +158,7 @@ def test_graph_rejects_learned_and_profile():
         dt.sort_u32(x, dt.make_opts(graph=1, profile=1, stats=dt.Stats()))
 
 
-@pytest.mark.parametrize("tile", [1, 2, 3, 4])
+@pytest.mark.parametrize("tile", [1, 2, 3, 4, 5])
 def test_tile_shapes(tile):
     require_gpu()
     say(f"tile shape {tile}")

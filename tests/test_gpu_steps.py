@@ -176,6 +176,58 @@ def test_step_leaf(wide, vals):
         assert np.array_equal(h(ov), exp_v)
 
 
+def _prefix_case(kind, rs, wide):
+    """Leaves whose keys differ in more than 16 bits, built to exercise the
+    prefix sort and its run fix-up: runs of equal top-16-bit prefix of chosen
+    lengths (FIX_MAX = 32 is the longest run the fix-up sorts; longer runs with
+    a descent take the full radix passes), and runs of equal keys."""
+    bits = 64 if wide else 32
+    hb = bits - 16
+    sizes = [4096, 4096, 300, 1000, 777]
+    parts = []
+    for i, sz in enumerate(sizes):
+        low = rs.integers(0, 2 ** hb, sz, dtype=np.uint64)
+        if kind == "unique":       # prefixes (nearly) unique: few or no runs to fix
+            pre = rs.integers(0, 2 ** 16, sz, dtype=np.uint64)
+        elif kind == "run32":      # runs of exactly 32 equal prefixes, lows out of order
+            pre = np.repeat(rs.choice(2 ** 16, sz // 32 + 1, replace=False).astype(np.uint64), 32)[:sz]
+        elif kind == "run33":      # runs of 33: the fix-up must give way to full passes
+            pre = np.repeat(rs.choice(2 ** 16, sz // 33 + 1, replace=False).astype(np.uint64), 33)[:sz]
+        elif kind == "few":        # four prefixes, random lows: long runs
+            pre = rs.choice(np.array([5, 6, 900, 65535], np.uint64), sz)
+        else:                      # duplicates: 50 distinct keys repeated (runs hold no descent)
+            dist = rs.integers(0, 2 ** bits, 50, dtype=np.uint64)
+            parts.append(rs.choice(dist, sz))
+            continue
+        parts.append((pre << np.uint64(hb)) | low)
+    keys = np.concatenate(parts).astype(np.uint64 if wide else np.uint32)
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint64)
+    return keys, off, bits
+
+
+@pytest.mark.parametrize("kind", ["unique", "run32", "run33", "few", "dups"])
+@pytest.mark.parametrize("wide", [False, True])
+def test_step_leaf_prefix_fixup(kind, wide):
+    require_gpu()
+    lib = _lib()
+    rs = np.random.default_rng(77)
+    keys, off, bits = _prefix_case(kind, rs, wide)
+    n = keys.size
+    v = np.arange(n, dtype=np.uint64 if wide else np.uint32)
+    exp_k, exp_v = S.segmented_sort(keys, off, v)
+    dk = dev_u64(keys) if wide else dev_u32(keys)
+    dv = dev_u64(v) if wide else dev_u32(v)
+    do = dev_u64(off)
+    ok, ov = torch.empty_like(dk), torch.empty_like(dv)
+    say(f"leaf prefix fix-up {kind} wide={wide}")
+    f = lib.dtsort_step_leaf_u64 if wide else lib.dtsort_step_leaf_u32
+    assert f(dk.data_ptr(), dv.data_ptr(), do.data_ptr(), len(off) - 1, bits, ok.data_ptr(), ov.data_ptr(),
+             _stream()) == 0
+    h = host_u64 if wide else host_u32
+    assert np.array_equal(h(ok), exp_k)
+    assert np.array_equal(h(ov), exp_v)
+
+
 @pytest.mark.parametrize("seed", range(6))
 def test_step_dtmerge(seed):
     require_gpu()

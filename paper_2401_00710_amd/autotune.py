@@ -2,8 +2,10 @@
 
 For every record layout (32-bit keys, 64-bit keys, 64-bit pairs, the batched
 32-bit form) and size class it times whole sorts of seeded synthetic inputs
-through the C ABI and picks, by coordinate descent, the scatter tile shape,
-then the digit width, then the base-case cutoff.  The winners are written as
+through the C ABI (the score of a parameter set is the summed time of a
+uniform and a Zipf-skewed input of the class size) and picks, by coordinate
+descent, the scatter tile shape, then the digit width, then the base-case
+cutoff.  The winners are written as
 rows of the text table the library reads when dtsort_opts.tuned = 1:
 
     key_bytes val_bytes segmented log2n_lo log2n_hi digit_bits lds_cutoff tile_shape
@@ -32,21 +34,23 @@ def _cutoffs(kb, vb):
 
 
 def _inputs(torch, W, kb, vb, seg, n, dev):
-    """Half uniform, half Zipf-skewed keys (heavy duplicates), seeded."""
+    """Seeded inputs a candidate is timed on (the score is the summed time):
+    uniform keys and Zipf-skewed keys (heavy duplicates) of the class size,
+    or the batched workload."""
     if seg:
         c = W.make_config("segmented_u32", seed=0, device=dev)
-        return dict(keys=c["keys"].to(torch.int32), offsets=c["offsets"], vals=None)
-    half = n // 2
-    if kb == 4:
-        a = W.uniform_u32(half, seed=1, device=dev)
-        b = W.zipf_u32(n - half, 1.0, max(n - half, 2), seed=2, device=dev)
-        k = torch.cat([a, b]).to(torch.int32)
-    else:
-        a = W.uniform_u64(half, seed=1, device=dev)
-        b = W.zipf_u64(n - half, 1.0, max(n - half, 2), seed=2, device=dev)
-        k = torch.cat([a, b])
-    v = torch.arange(n, dtype=torch.int64, device=dev) if vb else None
-    return dict(keys=k, offsets=None, vals=v)
+        return [dict(keys=c["keys"].to(torch.int32), offsets=c["offsets"], vals=None)]
+    out = []
+    for kind in ("uniform", "zipf"):
+        if kb == 4:
+            k = (W.uniform_u32(n, seed=1, device=dev) if kind == "uniform"
+                 else W.zipf_u32(n, 1.0, n, seed=2, device=dev)).to(torch.int32)
+        else:
+            k = (W.uniform_u64(n, seed=1, device=dev) if kind == "uniform"
+                 else W.zipf_u64(n, 1.0, n, seed=2, device=dev))
+        v = torch.arange(n, dtype=torch.int64, device=dev) if vb else None
+        out.append(dict(keys=k, offsets=None, vals=v))
+    return out
 
 
 def _time(dt, torch, case, inp, work, vwork, params, reps):
@@ -94,13 +98,17 @@ def tune(sizes, reps, log):
     plan = [(c, cl) for c in cases for cl in classes] + [((4, 0, 1), (0, 63, 0))]
     for case, (lo, hi, n) in plan:
         kb, vb, seg = case
-        inp = _inputs(torch, W, kb, vb, seg, n, dev)
-        work = torch.empty_like(inp["keys"])
-        vwork = torch.empty_like(inp["vals"]) if inp["vals"] is not None else None
+        inps = _inputs(torch, W, kb, vb, seg, n, dev)
+        work = torch.empty_like(inps[0]["keys"])
+        vwork = torch.empty_like(inps[0]["vals"]) if inps[0]["vals"] is not None else None
+
+        def score(p):
+            return sum(_time(dt, torch, case, inp, work, vwork, p, reps) for inp in inps)
+
         best = dict(digit_bits=8, lds_cutoff=0, tile_shape=1)
         if seg:
             best["graph"] = 1
-        t_best = _time(dt, torch, case, inp, work, vwork, best, reps)
+        t_best = score(best)
         tried = {json.dumps(best, sort_keys=True): t_best}
         for key, values in (("tile_shape", TILES), ("digit_bits", DIGITS), ("lds_cutoff", _cutoffs(kb, vb))):
             for v in values:
@@ -109,16 +117,16 @@ def tune(sizes, reps, log):
                 tag = json.dumps(p, sort_keys=True)
                 if tag in tried:
                     continue
-                t = _time(dt, torch, case, inp, work, vwork, p, reps)
+                t = score(p)
                 tried[tag] = t
-                log(f"  {case} n={inp['keys'].numel()} {p} {t:.3f} ms")
+                log(f"  {case} n={work.numel()} {p} {t:.3f} ms")
                 if t < t_best:
                     best, t_best = p, t
         log(f"{case} log2n [{lo},{hi}] best {best} {t_best:.3f} ms")
         rows.append((kb, vb, seg, lo, hi, best["digit_bits"], best["lds_cutoff"], best["tile_shape"]))
-        report.append(dict(case=case, n=int(inp["keys"].numel()), best=best, ms=t_best,
+        report.append(dict(case=case, n=int(work.numel()), best=best, ms=t_best,
                            tried={k: round(v, 4) for k, v in tried.items()}))
-        del inp, work, vwork
+        del inps, work, vwork
         torch.cuda.empty_cache()
     return rows, report
 

@@ -20,7 +20,6 @@ namespace dts {
 
 constexpr int NP = 4353;
 constexpr int OW1 = 0, OB1 = 64, OW2 = 128, OB2 = 128 + 4096, OW3 = 128 + 4096 + 64, OB3 = 128 + 4096 + 128;
-constexpr int GT = 128;  // samples (threads) per gradient workgroup
 
 __device__ inline double u01(uint64_t h, uint64_t i) {
   return (double)(mix64(h + (i + 1) * GOLD) >> 11) * (1.0 / 9007199254740992.0);
@@ -81,119 +80,164 @@ __global__ void k_mlp_data(const K* sk, uint32_t n, int kb, float* x, float* y) 
   }
 }
 
-// Forward + backward for GT samples per workgroup; writes this workgroup's
+// Forward + backward for GS samples per workgroup; writes this workgroup's
 // partial gradient (and partial loss at index NP) to part[blockIdx.x].
-// Samples: j = blockIdx.x * GT + t < batch; data index j*stride + off
+// Samples: j = blockIdx.x * GS + s < batch; data index j*stride + off
 // (stride 0 = contiguous).  The mean is over `batch`.
-__global__ __launch_bounds__(GT) void k_mlp_grad(const float* __restrict__ p, const float* __restrict__ x,
-                                                 const float* __restrict__ y, uint32_t batch, uint32_t stride,
-                                                 uint32_t off, float* __restrict__ part) {
+//
+// The three 64-wide products of a step (Z2 = H1 W2^T, dW2 = dZ2^T H1,
+// dH1 = dZ2 W2) run as register tiles: thread t owns rows 4*(t/16).. and
+// columns 4*(t%16).. of a 64 x 64 result and streams the shared dimension
+// from LDS (rows padded to 65 floats against bank conflicts).  Every sum over
+// samples is taken in sample order, so results are deterministic.
+constexpr int GS = 64;     // samples per gradient workgroup
+constexpr int GTH = 256;   // threads per gradient workgroup
+constexpr int LP = 65;     // padded LDS row
+
+__global__ __launch_bounds__(GTH) void k_mlp_grad(const float* __restrict__ p, const float* __restrict__ x,
+                                                  const float* __restrict__ y, uint32_t batch, uint32_t stride,
+                                                  uint32_t off, float* __restrict__ part) {
   __shared__ float P[NP];
-  __shared__ float A[GT][65];  // h1, later dz1 * x
-  __shared__ float B[GT][65];  // dz2, later d * h2
-  __shared__ float red[GT / WAVE];
+  __shared__ float W2s[64 * LP];  // W2 rows (output unit o), padded
+  __shared__ float H1[GS * LP];   // h1[s][i]
+  __shared__ float Z2[GS * LP];   // z2[s][o], later dz1[s][i]
+  __shared__ float DZ[GS * LP];   // dz2[s][o]
+  __shared__ float XS[GS], D[GS], ERR2[GS];
   const int t = threadIdx.x;
-  for (int i = t; i < NP; i += GT) P[i] = p[i];
+  for (int i = t; i < NP; i += GTH) P[i] = p[i];
   __syncthreads();
-  const uint32_t j = blockIdx.x * GT + t;
-  const bool valid = j < batch;
-  const uint32_t di = stride ? j * stride + off : j;
-  const float xs = valid ? x[di] : 0.0f;
-  const float ys = valid ? y[di] : 0.0f;
-  float h1[64], z2[64];
-#pragma unroll
-  for (int i = 0; i < 64; ++i) h1[i] = fmaxf(fmaf(P[OW1 + i], xs, P[OB1 + i]), 0.0f);
-#pragma unroll 4
-  for (int o = 0; o < 64; ++o) {
-    float s = P[OB2 + o];
-#pragma unroll
-    for (int i = 0; i < 64; ++i) s = fmaf(P[OW2 + o * 64 + i], h1[i], s);
-    z2[o] = s;
-  }
-  float yh = P[OB3];
-#pragma unroll
-  for (int o = 0; o < 64; ++o) yh = fmaf(P[OW3 + o], fmaxf(z2[o], 0.0f), yh);
-  const float err = valid ? (yh - ys) : 0.0f;
-  const float d = 2.0f * err / (float)batch;
-  // dz2 (kept in z2's registers after h2 has been used) and B = dz2
-#pragma unroll
-  for (int o = 0; o < 64; ++o) {
-    const float dz = z2[o] > 0.0f ? d * P[OW3 + o] : 0.0f;
-    A[t][o] = h1[o];
-    B[t][o] = dz;
-  }
-  // dh1 = W2^T dz2 -> dz1
-  float dz1[64];
-#pragma unroll
-  for (int i = 0; i < 64; ++i) dz1[i] = 0.0f;
-#pragma unroll 4
-  for (int o = 0; o < 64; ++o) {
-    const float dz = B[t][o];
-#pragma unroll
-    for (int i = 0; i < 64; ++i) dz1[i] = fmaf(P[OW2 + o * 64 + i], dz, dz1[i]);
+  for (int e = t; e < 4096; e += GTH) W2s[(e >> 6) * LP + (e & 63)] = P[OW2 + e];
+  if (t < GS) {
+    const uint32_t j = blockIdx.x * GS + t;
+    const uint32_t di = stride ? j * stride + off : j;
+    XS[t] = j < batch ? x[di] : 0.0f;
   }
   __syncthreads();
+  for (int e = t; e < GS * 64; e += GTH) {
+    const int sm = e >> 6, i = e & 63;
+    H1[sm * LP + i] = fmaxf(fmaf(P[OW1 + i], XS[sm], P[OB1 + i]), 0.0f);
+  }
+  __syncthreads();
+  const int r0 = (t / 16) * 4, c0 = (t % 16) * 4;
+  // Z2[s][o] = b2[o] + sum_i W2[o][i] h1[s][i]
+  {
+    float acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] = P[OB2 + c0 + b];
+    for (int i = 0; i < 64; ++i) {
+      float hv[4], wv[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) hv[a] = H1[(r0 + a) * LP + i];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) wv[b] = W2s[(c0 + b) * LP + i];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = fmaf(wv[b], hv[a], acc[a][b]);
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) Z2[(r0 + a) * LP + c0 + b] = acc[a][b];
+  }
+  __syncthreads();
+  // output, error and d = dLoss/dyhat per sample
+  if (t < GS) {
+    const uint32_t j = blockIdx.x * GS + t;
+    const uint32_t di = stride ? j * stride + off : j;
+    float yh = P[OB3];
+    for (int o = 0; o < 64; ++o) yh = fmaf(P[OW3 + o], fmaxf(Z2[t * LP + o], 0.0f), yh);
+    const float err = j < batch ? yh - y[di] : 0.0f;
+    D[t] = 2.0f * err / (float)batch;
+    ERR2[t] = err * err / (float)batch;
+  }
+  __syncthreads();
+  for (int e = t; e < GS * 64; e += GTH) {
+    const int sm = e >> 6, o = e & 63;
+    DZ[sm * LP + o] = Z2[sm * LP + o] > 0.0f ? D[sm] * P[OW3 + o] : 0.0f;
+  }
   float* out = part + (size_t)blockIdx.x * (NP + 1);
-  // dW2[o][i] = sum_s B[s][o] A[s][i]; db2[o] = sum_s B[s][o]
-  for (int e = t; e < 4096; e += GT) {
-    const int o = e >> 6, i = e & 63;
-    float s = 0.0f;
-    for (int r = 0; r < GT; ++r) s = fmaf(B[r][o], A[r][i], s);
-    out[OW2 + e] = s;
-  }
   if (t < 64) {
-    float s = 0.0f;
-    for (int r = 0; r < GT; ++r) s += B[r][t];
-    out[OB2 + t] = s;
-  }
-  __syncthreads();
-  // second pass: A = dz1 (masked), B = d * h2
-#pragma unroll
-  for (int i = 0; i < 64; ++i) {
-    A[t][i] = h1[i] > 0.0f ? dz1[i] : 0.0f;
-    B[t][i] = d * fmaxf(z2[i], 0.0f);
-  }
-  __syncthreads();
-  if (t < 64) {
-    float sb = 0.0f, s3 = 0.0f;
-    for (int r = 0; r < GT; ++r) {
-      sb += A[r][t];
-      s3 += B[r][t];
-    }
-    out[OB1 + t] = sb;
+    // dW3[o] = sum_s d_s relu(z2[s][o])
+    float s3 = 0.0f;
+    for (int sm = 0; sm < GS; ++sm) s3 = fmaf(D[sm], fmaxf(Z2[sm * LP + t], 0.0f), s3);
     out[OW3 + t] = s3;
-  }
-  // dW1[i] = sum_s dz1[s][i] * x_s: scale A rows by x_s, then column sums
-  __syncthreads();
-#pragma unroll
-  for (int i = 0; i < 64; ++i) A[t][i] *= xs;
-  __syncthreads();
-  if (t < 64) {
-    float s = 0.0f;
-    for (int r = 0; r < GT; ++r) s += A[r][t];
-    out[OW1 + t] = s;
-  }
-  // db3 = sum d ; loss = sum err^2 / batch
-  float db3 = d, ls = err * err / (float)batch;
-#pragma unroll
-  for (int o = WAVE / 2; o > 0; o >>= 1) {
-    db3 += __shfl_xor(db3, o, WAVE);
-    ls += __shfl_xor(ls, o, WAVE);
-  }
-  __shared__ float red2[GT / WAVE];
-  if ((t & (WAVE - 1)) == 0) {
-    red[t / WAVE] = db3;
-    red2[t / WAVE] = ls;
-  }
-  __syncthreads();
-  if (t == 0) {
-    float a = 0.0f, b = 0.0f;
-    for (int w = 0; w < GT / WAVE; ++w) {
-      a += red[w];
-      b += red2[w];
+  } else if (t == 64) {
+    float db3 = 0.0f, ls = 0.0f;
+    for (int sm = 0; sm < GS; ++sm) {
+      db3 += D[sm];
+      ls += ERR2[sm];
     }
-    out[OB3] = a;
-    out[NP] = b;
+    out[OB3] = db3;
+    out[NP] = ls;
+  }
+  __syncthreads();
+  // dW2[o][i] = sum_s dz2[s][o] h1[s][i]; db2[o] = sum_s dz2[s][o]
+  {
+    float acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] = 0.0f;
+    for (int sm = 0; sm < GS; ++sm) {
+      float dv[4], hv[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) dv[a] = DZ[sm * LP + r0 + a];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) hv[b] = H1[sm * LP + c0 + b];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = fmaf(dv[a], hv[b], acc[a][b]);
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) out[OW2 + (r0 + a) * 64 + c0 + b] = acc[a][b];
+  }
+  if (t < 64) {
+    float sb = 0.0f;
+    for (int sm = 0; sm < GS; ++sm) sb += DZ[sm * LP + t];
+    out[OB2 + t] = sb;
+  }
+  // dz1[s][i] = (h1[s][i] > 0) * sum_o W2[o][i] dz2[s][o]  (into Z2's space)
+  {
+    float acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] = 0.0f;
+    for (int o = 0; o < 64; ++o) {
+      float dv[4], wv[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) dv[a] = DZ[(r0 + a) * LP + o];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) wv[b] = W2s[o * LP + c0 + b];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = fmaf(wv[b], dv[a], acc[a][b]);
+    }
+    __syncthreads();  // every thread is done reading Z2 (dW3 above)
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        Z2[(r0 + a) * LP + c0 + b] = H1[(r0 + a) * LP + c0 + b] > 0.0f ? acc[a][b] : 0.0f;
+  }
+  __syncthreads();
+  // dW1[i] = sum_s dz1[s][i] x_s; db1[i] = sum_s dz1[s][i]
+  if (t < 64) {
+    float s1 = 0.0f;
+    for (int sm = 0; sm < GS; ++sm) s1 = fmaf(Z2[sm * LP + t], XS[sm], s1);
+    out[OW1 + t] = s1;
+  } else if (t < 128) {
+    const int i = t - 64;
+    float sb = 0.0f;
+    for (int sm = 0; sm < GS; ++sm) sb += Z2[sm * LP + i];
+    out[OB1 + i] = sb;
   }
 }
 
@@ -257,8 +301,8 @@ struct MlpBufs {
 
 int mlp_loss_grad(const float* p, const float* x, const float* y, uint32_t n, float* grad, float* loss, float* part,
                   hipStream_t s) {
-  const uint32_t nwg = (n + GT - 1) / GT;
-  hipLaunchKernelGGL(k_mlp_grad, dim3(nwg), dim3(GT), 0, s, p, x, y, n, 0u, 0u, part);
+  const uint32_t nwg = (n + GS - 1) / GS;
+  hipLaunchKernelGGL(k_mlp_grad, dim3(nwg), dim3(GTH), 0, s, p, x, y, n, 0u, 0u, part);
   hipLaunchKernelGGL(k_mlp_reduce, dim3((NP + 1 + 255) / 256), dim3(256), 0, s, part, nwg, (float*)nullptr,
                      (float*)nullptr, (float*)nullptr, grad, loss, 0, 0, 0.0f);
   return hipGetLastError() == hipSuccess ? 0 : -1;
@@ -276,9 +320,9 @@ void mlp_train(const float* x, const float* y, uint32_t n, uint64_t seed, int st
   (void)hipMemsetAsync(m, 0, sizeof(float) * NP, s);
   (void)hipMemsetAsync(v, 0, sizeof(float) * NP, s);
   const uint32_t stride = n / batch;
-  const uint32_t nwg = (batch + GT - 1) / GT;
+  const uint32_t nwg = (batch + GS - 1) / GS;
   for (int st = 0; st < steps; ++st) {
-    hipLaunchKernelGGL(k_mlp_grad, dim3(nwg), dim3(GT), 0, s, (const float*)p, x, y, batch, stride,
+    hipLaunchKernelGGL(k_mlp_grad, dim3(nwg), dim3(GTH), 0, s, (const float*)p, x, y, batch, stride,
                        (uint32_t)(st % stride), part);
     hipLaunchKernelGGL(k_mlp_reduce, dim3((NP + 1 + 255) / 256), dim3(256), 0, s, (const float*)part, nwg, p, m, v,
                        (float*)nullptr, losses ? losses + st : (float*)nullptr, 1, st + 1, lr);
@@ -319,7 +363,7 @@ int dtsort_mlp_loss_grad(const float* params, const float* x, const float* y, si
   if (!params || !x || !y || !grad || !loss || n == 0 || n >= (1u << 31)) return DTSORT_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   TmpF tmp;
-  const size_t nwg = (n + dts::GT - 1) / dts::GT;
+  const size_t nwg = (n + dts::GS - 1) / dts::GS;
   float* part = tmp.get(nwg * (dts::NP + 1));
   if (!part) return DTSORT_ENOMEM;
   if (dts::mlp_loss_grad(params, x, y, (uint32_t)n, grad, loss, part, s)) return DTSORT_EHIP;
@@ -344,7 +388,7 @@ int dtsort_mlp_train_u64(const uint64_t* sorted_keys, size_t n, uint64_t seed, i
   float* y = tmp.get(n);
   float* m = tmp.get(dts::NP);
   float* v = tmp.get(dts::NP);
-  float* part = tmp.get(((size_t)batch + dts::GT - 1) / dts::GT * (dts::NP + 1));
+  float* part = tmp.get(((size_t)batch + dts::GS - 1) / dts::GS * (dts::NP + 1));
   if (!x || !y || !m || !v || !part) return DTSORT_ENOMEM;
   dts::mlp_data<uint64_t>(sorted_keys, (uint32_t)n, 64, x, y, s);
   dts::mlp_train(x, y, (uint32_t)n, seed, steps, (uint32_t)batch, lr, params, m, v, part, losses, s);

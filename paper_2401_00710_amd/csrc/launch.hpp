@@ -118,7 +118,7 @@ template <typename K>
 void learned_kernels_judge(Task* task, uint8_t* tab, const K* held, uint32_t nh, const uint64_t* spl, void* info,
                            const float* losses, int steps, hipStream_t s);
 constexpr int MLP_PARAMS = 4353;
-constexpr int MLP_GT = 128;
+constexpr int MLP_GT = 64;  // samples per gradient workgroup (partial-gradient buffer sizing)
 
 // Tile sizes of the distribution kernels (records per tile) by key width.
 template <typename K, typename V>

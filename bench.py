@@ -2,20 +2,22 @@
 """Benchmark of the DovetailSort hot path on one MI355X.
 
 One "step" = one complete sort (every level: sampling, counting sort,
-recursion, leaf sorts, dovetail merges) of the workload, with the input
-already resident in HBM.  Before every step the input is restored from a
-pristine device copy (outside the timed region); each step is bracketed by
-stream synchronisations and timed with HIP events on the sort's stream.
+recursion, leaf sorts, dovetail merges) of each input of the workload, with
+the inputs already resident in HBM.  Before every sort its input is restored
+from a pristine device copy (outside the timed region); each sort is
+bracketed by stream synchronisations and timed with HIP events on the sort's
+stream; the step time is the sum.
 
 Prints ONE JSON line (rank 0, N=1):
-  value      G keys/s of the primary workload (10^9 uint32 keys, uniform)
+  value      G keys/s of the primary workload: 10^9 uint32 keys in two inputs
+             (uniform, and Zipf s = 1 over ranks 1..10^9); a step sorts both
   roofline   the scatter kernel (the dominant kernel): algorithmic bytes per
              launch / its average launch time, measured with HIP events in a
-             profiled extra run, against the 8 TB/s HBM peak
+             profiled extra run of each input, against the 8 TB/s HBM peak
   cpu_baseline  the CPU oracle (numpy stable sort, one core) on a bounded
-             sample of the same workload
-  extra      the other workloads (Zipf keys, 64-bit pairs, batched vs
-             per-instance calls, learned vs sampling partitioner)
+             sample of the same inputs
+  extra      the other workloads (64-bit pairs, batched vs per-instance calls,
+             learned vs sampling partitioner)
 """
 from __future__ import annotations
 
@@ -59,10 +61,12 @@ def timed_sorts(sortfn, src, work, steps, warmup, extra_src=None, extra_work=Non
     return times
 
 
-def roofline_from_stats(st, kind=3):
-    ms = st.kernel_ms[kind]
-    nb = st.kernel_bytes[kind]
-    launches = st.kernel_launches[kind]
+def roofline_from_stats(stats, kind=3):
+    """Dominant kernel (the scatter): algorithmic bytes per launch / average
+    launch time, over the launches of the given profiled sorts."""
+    ms = sum(st.kernel_ms[kind] for st in stats)
+    nb = sum(st.kernel_bytes[kind] for st in stats)
+    launches = sum(int(st.kernel_launches[kind]) for st in stats)
     if ms <= 0 or launches == 0:
         return None
     gbs = nb / (ms / 1e3) / 1e9
@@ -79,19 +83,25 @@ def roofline_from_stats(st, kind=3):
             traffic = None
     return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": "k_scatter", "launches": int(launches),
+            "kernel": "k_scatter", "launches": launches,
             "bytes_per_launch": nb / launches, "avg_launch_ms": ms / launches}
 
 
-def cpu_baseline(keys_dev, n_sample):
+def cpu_baseline(srcs, n_sample):
+    """The CPU oracle (numpy stable sort, one thread) on the first n_sample / 2
+    keys of each input, scaled to G keys/s."""
     import numpy as np
     from oracle import sort as S  # the CPU oracle, timed as the reported baseline
-    k = keys_dev[:n_sample].cpu().numpy().view(np.uint32).copy()
-    t0 = time.perf_counter()
-    S.stable_sort_keys(k)
-    dt = time.perf_counter() - t0
-    return {"value": round(n_sample / dt / 1e9, 5), "unit": "Gkeys/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {n_sample} keys of the workload (numpy stable sort, {dt:.2f} s)"}
+    half = max(1, n_sample // 2)
+    dt = 0.0
+    for src in srcs.values():
+        k = src[:half].cpu().numpy().view(np.uint32).copy()
+        t0 = time.perf_counter()
+        S.stable_sort_keys(k)
+        dt += time.perf_counter() - t0
+    cnt = half * len(srcs)
+    return {"value": round(cnt / dt / 1e9, 5), "unit": "Gkeys/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {half} keys of each of the {len(srcs)} inputs (numpy stable sort, {dt:.2f} s)"}
 
 
 def main():
@@ -131,40 +141,56 @@ def main():
         base.update(kw)
         return dt.make_opts(**base)
 
-    # ---------------- primary workload: 10^9 uniform uint32 keys
-    log(f"generating uniform u32 n={n}")
-    src = W.uniform_u32(n, seed=0, device=dev).to(torch.int32)
-    work = torch.empty_like(src)
-    st = dt.Stats()
-    o = opts(stats=st)
-    log("timing uniform u32")
-    times = timed_sorts(lambda: dt.sort_u32(work, o), src, work, args.steps, args.warmup)
-    # correctness spot check of the last timed output (sortedness; multiset by checksum)
-    w64 = work.to(torch.int64) & 0xFFFFFFFF
-    ok = bool((w64[1:] >= w64[:-1]).all().item()) and int(w64.sum()) == int((src.to(torch.int64) & 0xFFFFFFFF).sum())
+    # ---------------- primary workload: 10^9 uint32 keys in two inputs,
+    # uniform and Zipf (s = 1 over ranks 1..10^9); a step sorts both
+    log(f"generating uniform and Zipf u32 n={n}")
+    srcs = {"uniform": W.uniform_u32(n, seed=0, device=dev).to(torch.int32),
+            "zipf1": W.zipf_u32(n, 1.0, n, seed=0, device=dev).to(torch.int32)}
+    work = torch.empty_like(srcs["uniform"])
+    st = {k: dt.Stats() for k in srcs}
+    log("timing the two inputs")
+    per = {k: [] for k in srcs}
+    for i in range(args.warmup + args.steps):
+        for k, src in srcs.items():
+            t = timed_sorts(lambda: dt.sort_u32(work, opts(stats=st[k])), src, work, 1, 0)[0]
+            if i >= args.warmup:
+                per[k].append(t)
+    times = [a + b for a, b in zip(per["uniform"], per["zipf1"])]
     ms = statistics.mean(times)
-    # profiled extra run for the roofline
-    work.copy_(src)
-    torch.cuda.synchronize()
-    pst = dt.Stats()
-    dt.sort_u32(work, opts(stats=pst, profile=1))
-    torch.cuda.synchronize()
-    roof = roofline_from_stats(pst)
-    kern = {k: {"ms": round(pst.kernel_ms[i], 4), "GBs": round(pst.kernel_bytes[i] / max(pst.kernel_ms[i], 1e-9) / 1e6, 1),
-                "launches": int(pst.kernel_launches[i])}
-            for i, k in enumerate(dt.Stats.KINDS) if pst.kernel_launches[i]}
-    alg_bytes = sum(pst.kernel_bytes[i] for i in (1, 3, 5, 6, 7))
+    # correctness spot check of the last output (Zipf): sorted, same sum
+    w64 = work.to(torch.int64) & 0xFFFFFFFF
+    ok = bool((w64[1:] >= w64[:-1]).all().item()) and int(w64.sum()) == int(
+        (srcs["zipf1"].to(torch.int64) & 0xFFFFFFFF).sum())
+    # profiled extra run of each input for the roofline
+    prof = {}
+    for k, src in srcs.items():
+        work.copy_(src)
+        torch.cuda.synchronize()
+        prof[k] = dt.Stats()
+        dt.sort_u32(work, opts(stats=prof[k], profile=1))
+        torch.cuda.synchronize()
+    roof = roofline_from_stats(list(prof.values()))
+    kern = {}
+    for i, kd in enumerate(dt.Stats.KINDS):
+        ms_k = sum(p.kernel_ms[i] for p in prof.values())
+        nb = sum(p.kernel_bytes[i] for p in prof.values())
+        ln = sum(int(p.kernel_launches[i]) for p in prof.values())
+        if ln:
+            kern[kd] = {"ms": round(ms_k, 4), "GBs": round(nb / max(ms_k, 1e-9) / 1e6, 1), "launches": ln}
+    alg_bytes = sum(p.kernel_bytes[i] for p in prof.values() for i in (1, 3, 5, 6, 7))
     log("cpu baseline")
-    cpu = cpu_baseline(src, min(args.cpu_sample, n))
+    cpu = cpu_baseline(srcs, min(args.cpu_sample, n))
 
     extra = {}
     if not args.no_extra:
-        del work
-        extra = run_extra(dt, W, torch, np, n, args, opts, src)
+        del work, srcs
+        extra = run_extra(dt, W, torch, np, n, args, opts)
 
+    per_input = {k: {"ms": round(statistics.mean(v), 4), "Gkeys_s": round(n / (statistics.mean(v) / 1e3) / 1e9, 3),
+                     "levels": int(st[k].levels), "heavy_keys": int(st[k].heavy_keys)} for k, v in per.items()}
     out = {
         "metric": "G keys/s sorted at n=1e9 (plus % of HBM roofline of the dominant kernel)",
-        "value": round(n / (ms / 1e3) / 1e9, 3),
+        "value": round(2 * n / (ms / 1e3) / 1e9, 3),
         "unit": "Gkeys/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -175,13 +201,15 @@ def main():
         "vs_baseline": None,
         "dtype": "u32",
         "data": "synthetic",
-        "config": {"workload": "uniform_u32_1e9", "n": n, "key": "uint32", "distribution": "uniform [0, 2^32)",
-                   "seed": 0, "digit_bits": "autotuned" if tuned else dbits, "mode": "sampling"},
+        "config": {"workload": "u32_1e9_uniform_and_zipf1", "n_per_input": n, "key": "uint32",
+                   "inputs": ["uniform over [0, 2^32)", "Zipf s=1.0 over ranks 1..1e9, seeded bijection to keys"],
+                   "step": "one stable sort of each input (2e9 keys)", "seed": 0,
+                   "parameters": "tuning table" if tuned else f"digit_bits={dbits}", "mode": "sampling"},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "per_input": per_input,
         "step_ms_all": [round(t, 4) for t in times],
         "sorted_ok": ok,
-        "stats": {k: v for k, v in st.as_dict().items() if not k.startswith("kernel_") and v},
         "kernels": kern,
         "whole_sort_alg_GBs": round(alg_bytes / (ms / 1e3) / 1e9, 1),
         "extra": extra,
@@ -189,7 +217,7 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-ONCE = ("uniform_u32_1e9", "zipf1_u32_1e9", "exp_pairs_u64_1e9", "bexp_pairs_u64_1e9", "uniform_u64_1e9",
+ONCE = ("u32_1e9_uniform_and_zipf1", "uniform_u32_1e9", "zipf1_u32_1e9", "exp_pairs_u64_1e9", "bexp_pairs_u64_1e9", "uniform_u64_1e9",
         "mixture_u64_1e9", "mixture_u64_1e9_learned", "batched_4096_segments_graph", "batched_4096_segments")
 
 
@@ -204,6 +232,10 @@ def run_once(name, n):
         raise SystemExit(f"unknown workload {name}; one of {', '.join(ONCE)}")
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if name == "u32_1e9_uniform_and_zipf1":  # the primary workload: one sort of each input
+        for sub in ("uniform_u32_1e9", "zipf1_u32_1e9"):
+            run_once(sub, n)
+        return
     vals = vsrc = off = None
     kw = {}
     if name.startswith("batched"):
@@ -249,8 +281,8 @@ def run_once(name, n):
     print(json.dumps({"once": name, "ms": round(times[-1], 4)}), flush=True)
 
 
-def run_extra(dt, W, torch, np, n, args, opts, src_u32):
-    dev = src_u32.device
+def run_extra(dt, W, torch, np, n, args, opts):
+    dev = torch.device("cuda:0")
     res = {}
     steps = max(1, min(args.steps, 3))
 
@@ -261,14 +293,6 @@ def run_extra(dt, W, torch, np, n, args, opts, src_u32):
         res[name] = dict(ms=round(m, 3), Gkeys_s=round(info.pop("count", n) / (m / 1e3) / 1e9, 3), **info)
         return m
 
-    # Zipf s=1 over 10^9 ranks, bijected to 32-bit keys
-    log("generating zipf u32")
-    z = W.zipf_u32(n, 1.0, n, seed=0, device=dev).to(torch.int32)
-    zw = torch.empty_like(z)
-    st = dt.Stats()
-    one("zipf1_u32_1e9", lambda: dt.sort_u32(zw, opts(stats=st)), z, zw)
-    res["zipf1_u32_1e9"]["heavy_keys"] = int(st.heavy_keys)
-    del z, zw
     # 64-bit pairs: exponential and bit-exponential keys, value = index
     for name, gen in (("exp_pairs_u64_1e9", lambda: W.exponential_keys(n, 1e-5, seed=0, device=dev)),
                       ("bexp_pairs_u64_1e9", lambda: W.bit_exponential_keys(n, 0.1, seed=0, device=dev))):

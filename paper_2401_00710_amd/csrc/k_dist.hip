@@ -171,11 +171,19 @@ __global__ __launch_bounds__(T) void k_hist(LevelArgs a, const K* k0, const K* k
       K kk[ITEMS];
 #pragma unroll
       for (int i = 0; i < ITEMS; ++i) kk[i] = buf_load<K>(rk, (uint32_t)(i * T + threadIdx.x) * sizeof(K));
+      // every item's bucket first: the searches (splitters, heavy keys) of
+      // different items are independent and overlap their LDS latency
+      uint32_t bb[ITEMS];
+#pragma unroll
+      for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t e = base + i * T + threadIdx.x;
+        bb[i] = e < end ? bucket_of<K>(kk[i], pr, L, H, SPL) : 0u;
+      }
 #pragma unroll
       for (int i = 0; i < ITEMS; ++i) {
         const uint32_t e = base + i * T + threadIdx.x;
         const bool valid = e < end;
-        const uint32_t b = valid ? bucket_of<K>(kk[i], pr, L, H, SPL) : 0u;
+        const uint32_t b = bb[i];
         const uint64_t act = __ballot(valid);
         if (act == 0) continue;
         const int first = __builtin_ctzll(act);
@@ -376,12 +384,19 @@ __global__ __launch_bounds__(T, ((T == 512 || T == 1024) && ITEMS <= 8 &&
         }
         rank_pipelined<ITEMS>(bk, vl, wm, crow, pos);
       }
+      if constexpr (RANK != RANK_PIPE) {
+        // every item's bucket first: independent searches overlap their latency
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+          const uint32_t e = (uint32_t)striped_index<T, ITEMS>(i);
+          bk[i] = e < tile_n ? bucket_of<K>(kk[i], pr, L, H, SPL) : 0u;
+        }
+      }
 #pragma unroll
       for (int i = 0; i < (RANK == RANK_PIPE ? 0 : ITEMS); ++i) {
         const uint32_t e = (uint32_t)striped_index<T, ITEMS>(i);
         const bool valid = e < tile_n;
-        const uint32_t b = valid ? bucket_of<K>(kk[i], pr, L, H, SPL) : 0u;
-        bk[i] = b;
+        const uint32_t b = bk[i];
         uint64_t peers;
         if constexpr (RANK == RANK_LDS) {
           peers = lds_match(wm, b, valid);

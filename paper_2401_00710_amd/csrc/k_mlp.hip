@@ -86,13 +86,15 @@ __global__ void k_mlp_data(const K* sk, uint32_t n, int kb, float* x, float* y) 
 // (stride 0 = contiguous).  The mean is over `batch`.
 //
 // The three 64-wide products of a step (Z2 = H1 W2^T, dW2 = dZ2^T H1,
-// dH1 = dZ2 W2) run as register tiles: thread t owns rows 4*(t/16).. and
-// columns 4*(t%16).. of a 64 x 64 result and streams the shared dimension
-// from LDS (rows padded to 65 floats against bank conflicts).  Every sum over
-// samples is taken in sample order, so results are deterministic.
+// dH1 = dZ2 W2) run as register tiles: thread t owns ZR sample rows from
+// ZR*(t/16) (4 unit rows from 4*(t/16) for dW2) and 4 columns from 4*(t%16)
+// and streams the shared dimension from LDS (rows padded to 65 floats against
+// bank conflicts).  Every sum over samples is taken in sample order, so
+// results are deterministic.
 constexpr int GS = 64;     // samples per gradient workgroup
 constexpr int GTH = 256;   // threads per gradient workgroup
 constexpr int LP = 65;     // padded LDS row
+constexpr int ZR = GS / 16;  // sample rows per thread in the (sample x unit) products
 
 __global__ __launch_bounds__(GTH) void k_mlp_grad(const float* __restrict__ p, const float* __restrict__ x,
                                                   const float* __restrict__ y, uint32_t batch, uint32_t stride,
@@ -118,36 +120,38 @@ __global__ __launch_bounds__(GTH) void k_mlp_grad(const float* __restrict__ p, c
     H1[sm * LP + i] = fmaxf(fmaf(P[OW1 + i], XS[sm], P[OB1 + i]), 0.0f);
   }
   __syncthreads();
-  const int r0 = (t / 16) * 4, c0 = (t % 16) * 4;
+  const int c0 = (t % 16) * 4;
+  const int zr0 = (t / 16) * ZR;  // first sample row of this thread
+  const int r0 = (t / 16) * 4;    // first unit row of this thread (dW2)
   // Z2[s][o] = b2[o] + sum_i W2[o][i] h1[s][i]
   {
-    float acc[4][4];
+    float acc[ZR][4];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < ZR; ++a)
 #pragma unroll
       for (int b = 0; b < 4; ++b) acc[a][b] = P[OB2 + c0 + b];
     for (int i = 0; i < 64; ++i) {
-      float hv[4], wv[4];
+      float hv[ZR], wv[4];
 #pragma unroll
-      for (int a = 0; a < 4; ++a) hv[a] = H1[(r0 + a) * LP + i];
+      for (int a = 0; a < ZR; ++a) hv[a] = H1[(zr0 + a) * LP + i];
 #pragma unroll
       for (int b = 0; b < 4; ++b) wv[b] = W2s[(c0 + b) * LP + i];
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
+      for (int a = 0; a < ZR; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = fmaf(wv[b], hv[a], acc[a][b]);
     }
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < ZR; ++a)
 #pragma unroll
-      for (int b = 0; b < 4; ++b) Z2[(r0 + a) * LP + c0 + b] = acc[a][b];
+      for (int b = 0; b < 4; ++b) Z2[(zr0 + a) * LP + c0 + b] = acc[a][b];
   }
   __syncthreads();
   // output, error and d = dLoss/dyhat per sample
   if (t < GS) {
     const uint32_t j = blockIdx.x * GS + t;
     const uint32_t di = stride ? j * stride + off : j;
-    float yh = P[OB3];
+    float yh = P[OB3];  // one thread per sample
     for (int o = 0; o < 64; ++o) yh = fmaf(P[OW3 + o], fmaxf(Z2[t * LP + o], 0.0f), yh);
     const float err = j < batch ? yh - y[di] : 0.0f;
     D[t] = 2.0f * err / (float)batch;
@@ -204,28 +208,28 @@ __global__ __launch_bounds__(GTH) void k_mlp_grad(const float* __restrict__ p, c
   }
   // dz1[s][i] = (h1[s][i] > 0) * sum_o W2[o][i] dz2[s][o]  (into Z2's space)
   {
-    float acc[4][4];
+    float acc[ZR][4];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < ZR; ++a)
 #pragma unroll
       for (int b = 0; b < 4; ++b) acc[a][b] = 0.0f;
     for (int o = 0; o < 64; ++o) {
-      float dv[4], wv[4];
+      float dv[ZR], wv[4];
 #pragma unroll
-      for (int a = 0; a < 4; ++a) dv[a] = DZ[(r0 + a) * LP + o];
+      for (int a = 0; a < ZR; ++a) dv[a] = DZ[(zr0 + a) * LP + o];
 #pragma unroll
       for (int b = 0; b < 4; ++b) wv[b] = W2s[o * LP + c0 + b];
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
+      for (int a = 0; a < ZR; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = fmaf(wv[b], dv[a], acc[a][b]);
     }
     __syncthreads();  // every thread is done reading Z2 (dW3 above)
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < ZR; ++a)
 #pragma unroll
       for (int b = 0; b < 4; ++b)
-        Z2[(r0 + a) * LP + c0 + b] = H1[(r0 + a) * LP + c0 + b] > 0.0f ? acc[a][b] : 0.0f;
+        Z2[(zr0 + a) * LP + c0 + b] = H1[(zr0 + a) * LP + c0 + b] > 0.0f ? acc[a][b] : 0.0f;
   }
   __syncthreads();
   // dW1[i] = sum_s dz1[s][i] x_s; db1[i] = sum_s dz1[s][i]

@@ -76,8 +76,10 @@ def roofline_from_stats(stats, kind=3):
         try:
             import hashlib
             tr = json.load(open(TRAFFIC_FILE))
-            src = os.path.join(ROOT, tr["kernel_source"])
-            if hashlib.sha256(open(src, "rb").read()).hexdigest() == tr["kernel_source_sha256"]:
+            h = hashlib.sha256()
+            for f in tr["kernel_sources"]:
+                h.update(open(os.path.join(ROOT, f), "rb").read())
+            if h.hexdigest() == tr["kernel_sources_sha256"]:
                 traffic = tr.get("k_scatter_bytes_per_launch")
         except (OSError, ValueError, KeyError):
             traffic = None

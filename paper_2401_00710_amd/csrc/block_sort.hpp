@@ -71,11 +71,12 @@ __device__ void block_radix_sort(K (&k)[ITEMS], uint16_t (&ix)[ITEMS], int lo_bi
   uint32_t* tmp = cnt + WAVES * 256;
   unsigned long long* wm = mk + (RANK != RANK_BALLOT ? wv * 256 : 0);
   const int row0 = wv * WAVE * ITEMS;  // first element of this wave
+  // the counters start at zero; every pass zeroes them again after its last read
+  for (int i = btid<THREADS>(); i < WAVES * 256; i += THREADS) cnt[i] = 0;
+  bsync<THREADS>();
   for (int bit = lo_bit; bit < hi_bit; bit += 8) {
     const int nbits = min(8, hi_bit - bit);
     const uint32_t dmask = (1u << nbits) - 1u;
-    for (int i = btid<THREADS>(); i < WAVES * 256; i += THREADS) cnt[i] = 0;
-    bsync<THREADS>();
     uint32_t* wc = cnt + wv * 256;
     uint32_t pos[ITEMS];
     if constexpr (RANK == RANK_PIPE) {
@@ -158,6 +159,7 @@ __device__ void block_radix_sort(K (&k)[ITEMS], uint16_t (&ix)[ITEMS], int lo_bi
         if constexpr (IDX) ix[i] = si[e];
       }
     }
+    for (int i = btid<THREADS>(); i < WAVES * 256; i += THREADS) cnt[i] = 0;
     bsync<THREADS>();
   }
 }

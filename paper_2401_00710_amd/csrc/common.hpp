@@ -294,20 +294,17 @@ __device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t* tmp, uint32_t* 
     const int wv = threadIdx.x / WAVE;
     if (lane == WAVE - 1) tmp[wv] = x;
     __syncthreads();
-    if (threadIdx.x == 0) {
-      uint32_t s = 0;
-      for (int w = 0; w < WAVES; ++w) {
-        uint32_t t = tmp[w];
-        tmp[w] = s;
-        s += t;
-      }
-      tmp[WAVES] = s;
+    // every thread adds up the wave totals itself (broadcast reads, no serial step)
+    uint32_t before = 0, all = 0;
+#pragma unroll
+    for (int w = 0; w < WAVES; ++w) {
+      const uint32_t t = tmp[w];
+      before += w < wv ? t : 0u;
+      all += t;
     }
-    __syncthreads();
-    uint32_t r = x - v + tmp[wv];
-    *total = tmp[WAVES];
-    __syncthreads();
-    return r;
+    *total = all;
+    __syncthreads();  // tmp is free again for the caller's next scan
+    return x - v + before;
   }
 }
 

@@ -180,6 +180,21 @@ def main():
         if ln:
             kern[kd] = {"ms": round(ms_k, 4), "GBs": round(nb / max(ms_k, 1e-9) / 1e6, 1), "launches": ln}
     alg_bytes = sum(p.kernel_bytes[i] for p in prof.values() for i in (1, 3, 5, 6, 7))
+    # practical ceiling: a plain device copy of one input (reads and writes 4 bytes per key)
+    log("device copy")
+    cts = []
+    for _ in range(6):
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        work.copy_(srcs["uniform"])
+        e1.record()
+        torch.cuda.synchronize()
+        cts.append(e0.elapsed_time(e1))
+    copy_gbs = 2 * 4 * n / (statistics.median(cts[1:]) / 1e3) / 1e9
+    ceiling = {"device_copy_GBs": round(copy_gbs, 1),
+               "scatter_frac_of_copy": round(roof["achieved"] / copy_gbs, 4) if roof else None,
+               "sort_floor_frac": None}
     log("cpu baseline")
     cpu = cpu_baseline(srcs, min(args.cpu_sample, n))
 
@@ -188,6 +203,8 @@ def main():
         del work, srcs
         extra = run_extra(dt, W, torch, np, n, args, opts)
 
+    # one read and one write of every key per step, against the HBM peak
+    ceiling["sort_floor_frac"] = round(2 * 4 * 2 * n / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
     per_input = {k: {"ms": round(statistics.mean(v), 4), "Gkeys_s": round(n / (statistics.mean(v) / 1e3) / 1e9, 3),
                      "levels": int(st[k].levels), "heavy_keys": int(st[k].heavy_keys)} for k, v in per.items()}
     out = {
@@ -214,6 +231,7 @@ def main():
         "sorted_ok": ok,
         "kernels": kern,
         "whole_sort_alg_GBs": round(alg_bytes / (ms / 1e3) / 1e9, 1),
+        "practical_ceiling": ceiling,
         "extra": extra,
     }
     print(json.dumps(out), flush=True)
@@ -294,6 +312,26 @@ def run_extra(dt, W, torch, np, n, args, opts):
         m = statistics.mean(ts)
         res[name] = dict(ms=round(m, 3), Gkeys_s=round(info.pop("count", n) / (m / 1e3) / 1e9, 3), **info)
         return m
+
+    # the small workload (2^20 uniform u32, cache-resident): latency, six runs, median of the last five
+    small = W.make_config("uniform_u32_2p20", seed=0, device=dev)["keys"].to(torch.int32)
+    sw = torch.empty_like(small)
+    ts = timed_sorts(lambda: dt.sort_u32(sw, opts()), small, sw, 5, 1)
+    m = statistics.median(ts)
+    res["uniform_u32_2p20"] = dict(us=round(m * 1e3, 1), Gkeys_s=round(small.numel() / (m / 1e3) / 1e9, 3),
+                                   protocol="6 runs, median of the last 5")
+    # n sweep of uniform u32 (where launch overhead stops mattering): prefixes of one 2^30 input
+    big = W.uniform_u32(1 << 30, seed=0, device=dev).to(torch.int32)
+    bw = torch.empty_like(big)
+    sweep = {}
+    for lg in (20, 22, 24, 26, 28, 30):
+        m_ = 1 << lg
+        src_, w_ = big[:m_], bw[:m_]
+        ts = timed_sorts(lambda: dt.sort_u32(w_, opts()), src_, w_, 3, 1)
+        t_ = statistics.median(ts)
+        sweep[f"2^{lg}"] = dict(ms=round(t_, 4), Gkeys_s=round(m_ / (t_ / 1e3) / 1e9, 3))
+    res["n_sweep_uniform_u32"] = sweep
+    del small, sw, big, bw
 
     # 64-bit pairs: exponential and bit-exponential keys, value = index
     for name, gen in (("exp_pairs_u64_1e9", lambda: W.exponential_keys(n, 1e-5, seed=0, device=dev)),

@@ -238,7 +238,8 @@ def main():
 
 
 ONCE = ("u32_1e9_uniform_and_zipf1", "uniform_u32_1e9", "zipf1_u32_1e9", "exp_pairs_u64_1e9", "bexp_pairs_u64_1e9", "uniform_u64_1e9",
-        "mixture_u64_1e9", "mixture_u64_1e9_learned", "batched_4096_segments_graph", "batched_4096_segments")
+        "bexp_pairs_u64_1e9_learned", "mixture_u64_1e9", "mixture_u64_1e9_learned", "batched_4096_segments_graph",
+        "batched_4096_segments")
 
 
 def run_once(name, n):
@@ -277,6 +278,8 @@ def run_once(name, n):
                else W.bit_exponential_keys(n, 0.1, seed=0, device=dev))
         vsrc = torch.arange(n, dtype=torch.int64, device=dev)
         vals = torch.empty_like(vsrc)
+        if name.endswith("learned"):
+            kw = dict(mode=dt.MODE_LEARNED)
     work = torch.empty_like(src)
     o = dt.make_opts(tuned=1, **kw)
     times = []
@@ -343,6 +346,16 @@ def run_extra(dt, W, torch, np, n, args, opts):
         st = dt.Stats()
         one(name, lambda: dt.sort_pairs_u64(kw, vw, opts(stats=st)), k, kw, v, vw)
         res[name]["levels"] = int(st.levels)
+        if name.startswith("bexp"):
+            # the learned partitioner on the input whose bit lengths are geometric
+            sl = dt.Stats()
+            one(name + "_learned", lambda: dt.sort_pairs_u64(kw, vw, opts(stats=sl, mode=dt.MODE_LEARNED)), k, kw,
+                v, vw)
+            res[name + "_learned"].update(learned_used=int(sl.learned_used),
+                                          balance_learned=round(sl.learned_balance, 3),
+                                          balance_digit=round(sl.sampling_balance, 3),
+                                          training_ms=round(sl.learned_ms, 3), levels=int(sl.levels))
+            res["bexp_learned_speedup_vs_sampling"] = round(res[name]["ms"] / res[name + "_learned"]["ms"], 3)
         del k, v, kw, vw
     # batched: 4096 instances in one call vs one call per instance
     log("generating segmented")

@@ -16,7 +16,10 @@ n' records whose keys all share the bits at and above ``hi``:
    form of where every heavy bucket ends.
 
 Base cases (Section 3.5): no bits left, or n' at most the cutoff, which is
-handed to a stable comparison sort (the method must stay stable).
+handed to a stable comparison sort (the method must stay stable).  With
+``pair_leaves`` (the GPU path for 32-bit keys without values) a child
+subproblem of at most twice the cutoff is a base case too: the GPU sorts its
+two halves and merges them, a stable comparison sort of n' records.
 
 Readings of points the paper leaves open (each listed in the design notes):
 * digit width: gamma = clamp(floor((floor(log2 n') + 1) / 3), gmin, gmax), the
@@ -64,6 +67,7 @@ class Config:
     gmax: int = 11
     cutoff: int = 16384       # base-case threshold (theta)
     plain: bool = False       # heavy-key detection off (the paper's "Plain" ablation)
+    pair_leaves: bool = False  # children of at most 2 * cutoff records are base cases
 
     @property
     def sample_cap(self) -> int:
@@ -338,7 +342,8 @@ def dtsort(keys: np.ndarray, values: np.ndarray | None = None, cfg: Config | Non
 def _rec(k, v, off, n, hi, n_root, level, cfg, skip_disabled, st):
     if n <= 1 or hi == 0:                                  # all bits sorted
         return
-    if n <= cfg.cutoff:                                    # base case: stable sort
+    base = cfg.cutoff * (2 if (cfg.pair_leaves and level > 0) else 1)
+    if n <= base:                                          # base case: stable sort
         o = np.argsort(k[off:off + n], kind="stable")
         k[off:off + n] = k[off:off + n][o]
         if v is not None:

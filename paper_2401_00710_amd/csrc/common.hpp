@@ -125,6 +125,7 @@ struct LevelCounters {
   // statistics (accumulated)
   unsigned long long st_heavy_keys, st_heavy_records, st_leaf_records, st_copy_records, st_merge_records,
       st_overflow_records, st_tasks, st_distributed;
+  unsigned long long st_pair_records;  // records of paired leaves (also in st_leaf_records)
 };
 
 enum ErrBits : uint32_t {

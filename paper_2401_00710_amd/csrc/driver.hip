@@ -53,7 +53,7 @@ struct LevelKeep {
 // one recorded graph).
 struct Work {
   DevBuf tk;                      // ping-pong partner of keys (and values), unless the caller gives one
-  DevBuf tasks[2], units, cm, leaf[LEAF_CLASSES], copies, ctr;
+  DevBuf tasks[2], units, cm, leaf[LEAF_CLASSES + 1], copies, ctr;  // leaf[LEAF_PAIR]: paired halves
   std::vector<LevelKeep> lv;
 };
 
@@ -310,7 +310,7 @@ static void fill_caps(LevelArgs& a, uint32_t n_tasks, uint64_t total, int gmax, 
   const uint64_t nbc = (uint64_t)nb_cap(gmax);
   const uint64_t buckets = (uint64_t)n_tasks * nbc;
   a.caps.tasks = (uint32_t)std::min<uint64_t>(buckets, total / (cutoff + 1ull) + 1);
-  a.caps.leaf = (uint32_t)std::min<uint64_t>(buckets, total / 2 + 1);
+  a.caps.leaf = (uint32_t)std::min<uint64_t>(2 * buckets, total / 2 + 1);  // a paired bucket takes two entries
   a.caps.copies = (uint32_t)std::min<uint64_t>(buckets + total / (1u << 20) + 1, total + 1);
   a.caps.merges = (uint32_t)std::min<uint64_t>((uint64_t)n_tasks << (gmax - 1), total + 1);
   a.caps.munits = (uint32_t)(total / 4096 + a.caps.merges + 1);
@@ -330,7 +330,7 @@ static void add_stats(dtsort_stats* st, const LevelCounters& h, bool level) {
     st->records_copied += h.st_copy_records;
     st->overflow_records += h.st_overflow_records;
   }
-  for (int k = 0; k < LEAF_CLASSES; ++k) st->leaf_sorts += h.leaf[k];
+  for (int k = 0; k <= LEAF_PAIR; ++k) st->leaf_sorts += h.leaf[k];
   st->records_leaf_sorted += h.st_leaf_records;
 }
 
@@ -426,6 +426,7 @@ static int run_sort(Ctx* c, SortJob<K, V>& J, hipStream_t s, dtsort_stats* stats
   a.g_override = gover;
   a.cutoff = cutoff;
   for (int k = 0; k < LEAF_CLASSES; ++k) a.leaf_max[k] = leaf_cap<K, V>(k);
+  a.leaf_max[LEAF_PAIR] = pair_max<K, V>(cutoff);
   a.plain = o.mode == DTSORT_MODE_PLAIN;
   a.key_bits = J.key_bits;
   a.tile = P.tile;
@@ -456,14 +457,14 @@ static int run_sort(Ctx* c, SortJob<K, V>& J, hipStream_t s, dtsort_stats* stats
     const int gmax0 = plan_gamma((uint32_t)std::min<size_t>(n, 0xFFFFFFFFu), gover);
     fill_caps<K, V>(a, std::max<uint32_t>(J.n_seg, 1), cap_total, gmax0, cutoff);
     a.caps.tasks = J.n_seg + 1;
-    a.caps.leaf = J.n_seg + 1;
+    a.caps.leaf = 2 * J.n_seg + 2;  // a paired segment takes two entries
     a.caps.copies = J.n_seg + 1;
     if ((r = ensure(W.tasks[cur], sizeof(Task) * (size_t)a.caps.tasks, s))) return r;
-    for (int k = 0; k < LEAF_CLASSES; ++k)
+    for (int k = 0; k <= LEAF_PAIR; ++k)
       if ((r = ensure(W.leaf[k], sizeof(Leaf) * (size_t)a.caps.leaf, s))) return r;
     if ((r = ensure(W.copies, sizeof(Leaf) * (size_t)a.caps.copies, s))) return r;
     a.next = (Task*)W.tasks[cur].p;
-    for (int k = 0; k < LEAF_CLASSES; ++k) a.leaf[k] = (Leaf*)W.leaf[k].p;
+    for (int k = 0; k <= LEAF_PAIR; ++k) a.leaf[k] = (Leaf*)W.leaf[k].p;
     a.copies = (Leaf*)W.copies.p;
     a.ctr = dctr;
     launch_zero_counters(dctr, 1, s);
@@ -478,7 +479,9 @@ static int run_sort(Ctx* c, SortJob<K, V>& J, hipStream_t s, dtsort_stats* stats
     for (int k = 0; k < LEAF_CLASSES; ++k)
       launch_leaf<K, V>((Leaf*)W.leaf[k].p, &dctr[0].leaf[k], a.caps.leaf, std::min(h.leaf[k], a.caps.leaf), k,
                         J.bufs, s);
-    prof.end(2.0 * rec_bytes * (double)h.st_leaf_records);
+    launch_pairs<K, V>((Leaf*)W.leaf[LEAF_PAIR].p, &dctr[0].leaf[LEAF_PAIR], a.caps.leaf,
+                       std::min(h.leaf[LEAF_PAIR], a.caps.leaf), h.leaf[LEAF_PAIR] / 2, J.bufs, s);
+    prof.end(2.0 * rec_bytes * (double)(h.st_leaf_records + h.st_pair_records));
     HIPCHK(hipGetLastError());
     add_stats(stats, h, false);
     n_tasks = h.next_tasks;
@@ -541,7 +544,7 @@ static int run_sort(Ctx* c, SortJob<K, V>& J, hipStream_t s, dtsort_stats* stats
     if ((r = ensure(W.cm, 4 * cm_entries, s))) return r;
     if ((r = ensure(K_.tab, tab_bytes, s))) return r;
     if ((r = ensure(W.tasks[1 - cur], sizeof(Task) * (size_t)a.caps.tasks, s))) return r;
-    for (int k = 0; k < LEAF_CLASSES; ++k)
+    for (int k = 0; k <= LEAF_PAIR; ++k)
       if ((r = ensure(W.leaf[k], sizeof(Leaf) * (size_t)a.caps.leaf, s))) return r;
     if ((r = ensure(W.copies, sizeof(Leaf) * (size_t)a.caps.copies, s))) return r;
     if ((r = ensure(K_.merges, sizeof(Merge) * (size_t)a.caps.merges, s))) return r;
@@ -556,7 +559,7 @@ static int run_sort(Ctx* c, SortJob<K, V>& J, hipStream_t s, dtsort_stats* stats
     a.cols = cols;
     a.cm = (uint32_t*)W.cm.p;
     a.next = (Task*)W.tasks[1 - cur].p;
-    for (int k = 0; k < LEAF_CLASSES; ++k) a.leaf[k] = (Leaf*)W.leaf[k].p;
+    for (int k = 0; k <= LEAF_PAIR; ++k) a.leaf[k] = (Leaf*)W.leaf[k].p;
     a.copies = (Leaf*)W.copies.p;
     a.merges = (Merge*)K_.merges.p;
     a.spills = (Leaf*)K_.spills.p;
@@ -609,7 +612,9 @@ static int run_sort(Ctx* c, SortJob<K, V>& J, hipStream_t s, dtsort_stats* stats
     prof.begin(PK_LEAF);
     for (int k = 0; k < LEAF_CLASSES; ++k)
       launch_leaf<K, V>((Leaf*)W.leaf[k].p, &a.ctr->leaf[k], a.caps.leaf, h.leaf[k], k, J.bufs, s);
-    prof.end(2.0 * rec_bytes * (double)h.st_leaf_records);
+    launch_pairs<K, V>((Leaf*)W.leaf[LEAF_PAIR].p, &a.ctr->leaf[LEAF_PAIR], a.caps.leaf, h.leaf[LEAF_PAIR],
+                       h.leaf[LEAF_PAIR] / 2, J.bufs, s);
+    prof.end(2.0 * rec_bytes * (double)(h.st_leaf_records + h.st_pair_records));
     prof.begin(PK_COPY);
     launch_copy<K, V>((Leaf*)W.copies.p, &a.ctr->copies, a.caps.copies, h.copies, J.bufs, s);
     prof.end(2.0 * rec_bytes * (double)h.st_copy_records);
@@ -653,7 +658,7 @@ struct GPlan {
   Caps caps{};
   uint64_t tab_bytes = 0;
   uint32_t slot_bytes = 0;
-  uint32_t grid_tasks = 0, grid_units = 0, grid_leaf[LEAF_CLASSES] = {}, grid_copy = 0, grid_mpos = 0,
+  uint32_t grid_tasks = 0, grid_units = 0, grid_leaf[LEAF_CLASSES] = {}, grid_pair = 0, grid_copy = 0, grid_mpos = 0,
            grid_munit = 0, grid_spill = 0, grid_finish = 0;
 };
 
@@ -680,7 +685,7 @@ static GPlan graph_plan(const SortJob<K, V>& J, const Params& P) {
   const uint64_t tasks = n / (g.cutoff + 1ull) + 1;
   Caps& c = g.caps;
   c.tasks = (uint32_t)tasks;
-  c.leaf = (uint32_t)std::min<uint64_t>(tasks * nbc + J.n_seg + 1, n + 1);
+  c.leaf = (uint32_t)std::min<uint64_t>(2 * (tasks * nbc + J.n_seg + 1), n + 1);  // paired buckets: two entries
   c.copies = (uint32_t)std::min<uint64_t>(tasks * nbc + n / (1u << 20) + 1, n + 1);
   c.merges = (uint32_t)std::min<uint64_t>(tasks << (g.gmax - 1), n + 1);
   c.munits = (uint32_t)(n / 4096 + c.merges + 1);
@@ -698,6 +703,7 @@ static GPlan graph_plan(const SortJob<K, V>& J, const Params& P) {
   // sorters in a workgroup)
   const uint32_t per_cu[LEAF_CLASSES] = {16, 8, 4, 2, 2};
   for (int k = 0; k < LEAF_CLASSES; ++k) g.grid_leaf[k] = pg(per_cu[k], c.leaf);
+  g.grid_pair = pair_leaves<K, V>() ? pg(1, c.leaf / 2 + 1) : 0;
   g.grid_copy = pg(4, c.copies);
   g.grid_mpos = pg(8, c.merges);
   g.grid_munit = pg(4, c.munits);
@@ -739,12 +745,13 @@ static void graph_enqueue(Work& W, const GPlan& g, const SortJob<K, V>& J, const
   a.g_override = P.gover;
   a.cutoff = g.cutoff;
   for (int k = 0; k < LEAF_CLASSES; ++k) a.leaf_max[k] = leaf_cap<K, V>(k);
+  a.leaf_max[LEAF_PAIR] = pair_max<K, V>(g.cutoff);
   a.plain = J.o.mode == DTSORT_MODE_PLAIN;
   a.key_bits = J.key_bits;
   a.tile = P.tile;
   a.caps = g.caps;
   LevelCounters* dctr = (LevelCounters*)W.ctr.p;
-  for (int k = 0; k < LEAF_CLASSES; ++k) a.leaf[k] = (Leaf*)W.leaf[k].p;
+  for (int k = 0; k <= LEAF_PAIR; ++k) a.leaf[k] = (Leaf*)W.leaf[k].p;
   a.copies = (Leaf*)W.copies.p;
   launch_zero_counters(dctr, (uint32_t)g.levels + 1, s);
   if (J.seg) {
@@ -753,6 +760,8 @@ static void graph_enqueue(Work& W, const GPlan& g, const SortJob<K, V>& J, const
     launch_seed_segments<K, V>(a, J.seg, J.n_seg, J.n, s);
     for (int k = 0; k < LEAF_CLASSES; ++k)
       launch_leaf<K, V>((Leaf*)W.leaf[k].p, &dctr[0].leaf[k], g.caps.leaf, g.grid_leaf[k], k, J.bufs, s);
+    launch_pairs<K, V>((Leaf*)W.leaf[LEAF_PAIR].p, &dctr[0].leaf[LEAF_PAIR], g.caps.leaf,
+                       g.grid_leaf[LEAF_CLASSES - 1], g.grid_pair, J.bufs, s);
   } else {
     launch_root<K>((Task*)W.tasks[0].p, dctr, J.n, J.key_bits, plan_gamma((uint32_t)J.n, P.gover), s);
   }
@@ -779,6 +788,8 @@ static void graph_enqueue(Work& W, const GPlan& g, const SortJob<K, V>& J, const
     launch_children<K, V>(a, J.bufs, s);
     for (int k = 0; k < LEAF_CLASSES; ++k)
       launch_leaf<K, V>((Leaf*)W.leaf[k].p, &a.ctr->leaf[k], g.caps.leaf, g.grid_leaf[k], k, J.bufs, s);
+    launch_pairs<K, V>((Leaf*)W.leaf[LEAF_PAIR].p, &a.ctr->leaf[LEAF_PAIR], g.caps.leaf,
+                       g.grid_leaf[LEAF_CLASSES - 1], g.grid_pair, J.bufs, s);
     launch_copy<K, V>((Leaf*)W.copies.p, &a.ctr->copies, g.caps.copies, g.grid_copy, J.bufs, s);
     launch_merge_units((Merge*)K_.merges.p, &a.ctr->merges, g.caps.merges, g.grid_mpos, (uint2*)K_.munits.p, s);
   }

@@ -239,6 +239,77 @@ __global__ __launch_bounds__(T* SUB) void k_leaf(const Leaf* items, const uint32
   }
 }
 
+// ----------------------------------------------------------- pair merge
+// Second step of paired leaves: halves[2p] = [off, off + h) and
+// halves[2p + 1] = [off + h, off + c), both sorted in buffer `to`, merged into
+// buffer `pad` over [off, off + c) (c <= PAIR_MAX); on equal keys the first
+// half goes first, so the merge is stable.  The bucket is staged in LDS;
+// thread t produces outputs [t E, t E + E): it finds where the merge path
+// crosses diagonal t E by a binary search, merges E steps, and writes its
+// outputs back to LDS (one padding word per 32 keeps the lanes on distinct
+// banks) for a coalesced copy out.
+template <typename K>
+__global__ __launch_bounds__(1024) void k_pair_merge(const Leaf* halves, const uint32_t* count, uint32_t cap, K* k0,
+                                                     K* k1) {
+  constexpr int T = 1024, E = PAIR_MAX / T;
+  static_assert(E * T == (int)PAIR_MAX && E == 32, "one padding word per 32 outputs of a thread");
+  __shared__ K sa[PAIR_MAX + PAIR_MAX / 32];
+  const uint32_t n_pairs = min(*count, cap) / 2;
+  for (uint32_t pi = blockIdx.x; pi < n_pairs; pi += gridDim.x) {
+    const Leaf A = halves[2 * pi], B = halves[2 * pi + 1];
+    const int na = (int)A.size, n = (int)(A.size + B.size);
+    if (n > (int)PAIR_MAX) continue;  // never made by the child planning
+    const K* src = (A.to ? k1 : k0) + A.off;
+    K* dst = (A.pad ? k1 : k0) + A.off;
+    for (int e = threadIdx.x; e < n; e += T) sa[e] = src[e];
+    __syncthreads();
+    const K* a = sa;
+    const K* b = sa + na;
+    const int nb = n - na;
+    const int d = min((int)threadIdx.x * E, n);
+    // i = records of the first half among the first d outputs
+    int lo = max(0, d - nb), hi = min(d, na);
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (a[mid] <= b[d - 1 - mid]) {
+        lo = mid + 1;
+      } else {
+        hi = mid;
+      }
+    }
+    int i = lo, j = d - lo;
+    K out[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const bool take_a = j >= nb || (i < na && a[i] <= b[j]);
+      out[e] = take_a ? a[min(i, na - 1)] : b[min(j, nb - 1)];
+      i += take_a ? 1 : 0;
+      j += take_a ? 0 : 1;
+    }
+    __syncthreads();  // every read of the halves is done
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int p = d + e;
+      if (p < n) sa[p + (p >> 5)] = out[e];
+    }
+    __syncthreads();
+    for (int p = threadIdx.x; p < n; p += T) dst[p] = sa[p + (p >> 5)];
+    __syncthreads();
+  }
+}
+
+template <typename K, typename V>
+void launch_pairs(const Leaf* halves, const uint32_t* count, uint32_t cap, uint32_t grid_leaf, uint32_t grid_merge,
+                  Bufs<K, V> b, hipStream_t s) {
+  if constexpr (pair_leaves<K, V>()) {
+    if (grid_leaf == 0 || grid_merge == 0 || cap == 0) return;
+    launch_leaf<K, V>(halves, count, cap, grid_leaf, LEAF_CLASSES - 1, b, s);
+    hipLaunchKernelGGL((k_pair_merge<K>), dim3(grid_merge), dim3(1024), 0, s, halves, count, cap, b.k[0], b.k[1]);
+  } else {
+    (void)halves, (void)count, (void)cap, (void)grid_leaf, (void)grid_merge, (void)b, (void)s;
+  }
+}
+
 // ----------------------------------------------------------- finishing
 // Tasks still open after the last recorded level of the graph form: one
 // workgroup per task sorts it completely with a stable LSD radix sort
@@ -419,6 +490,8 @@ template void launch_plan<uint32_t>(const LevelArgs&, const uint32_t*, const uin
 template void launch_plan<uint64_t>(const LevelArgs&, const uint64_t*, const uint64_t*, int, hipStream_t);
 #define DTS_INST(K, V)                                                                                           \
   template void launch_leaf<K, V>(const Leaf*, const uint32_t*, uint32_t, uint32_t, int, Bufs<K, V>, hipStream_t); \
+  template void launch_pairs<K, V>(const Leaf*, const uint32_t*, uint32_t, uint32_t, uint32_t, Bufs<K, V>,         \
+                                   hipStream_t);                                                                \
   template void launch_finish<K, V>(const Task*, const uint32_t*, uint32_t, uint32_t, Bufs<K, V>, hipStream_t);
 DTS_INST(uint32_t, NoVal)
 DTS_INST(uint64_t, NoVal)

@@ -21,7 +21,7 @@ constexpr uint32_t COPY_PIECE = 1u << 20;   // records per copy item
 constexpr uint32_t MERGE_TILE = 4096;       // outputs per gather unit
 
 // Kinds of work a finished distribution hands on (one output list each).
-enum Kind : int { KD_TASK = 0, KD_LEAF0 = 1, KD_COPY = 1 + LEAF_CLASSES, KD_MERGE, KD_MUNIT, KD_SPILL, KD_N };
+enum Kind : int { KD_TASK = 0, KD_LEAF0 = 1, KD_COPY = 1 + LEAF_CLASSES, KD_MERGE, KD_MUNIT, KD_SPILL, KD_PAIR, KD_N };
 
 struct Child {
   uint64_t off;
@@ -47,6 +47,10 @@ __device__ inline int child_kind(const LevelArgs& a, uint32_t c, int hi, int buf
       if (c <= a.leaf_max[k]) cls = k;
     return KD_LEAF0 + cls;
   }
+  if (c <= a.leaf_max[LEAF_PAIR]) {  // two half leaves and their merge (0: not for this layout)
+    *units = 2;
+    return KD_PAIR;
+  }
   return KD_TASK;
 }
 
@@ -56,12 +60,13 @@ __device__ inline uint32_t* kind_counter(LevelCounters* ctr, int kind) {
   if (kind == KD_COPY) return &ctr->copies;
   if (kind == KD_MERGE) return &ctr->merges;
   if (kind == KD_MUNIT) return &ctr->merge_units;
+  if (kind == KD_PAIR) return &ctr->leaf[LEAF_PAIR];
   return &ctr->spills;
 }
 
 __device__ inline uint32_t kind_cap(const LevelArgs& a, int kind) {
   if (kind == KD_TASK) return a.caps.tasks;
-  if (kind >= KD_LEAF0 && kind < KD_LEAF0 + LEAF_CLASSES) return a.caps.leaf;
+  if ((kind >= KD_LEAF0 && kind < KD_LEAF0 + LEAF_CLASSES) || kind == KD_PAIR) return a.caps.leaf;
   if (kind == KD_COPY) return a.caps.copies;
   if (kind == KD_MERGE) return a.caps.merges;
   if (kind == KD_MUNIT) return a.caps.munits;
@@ -104,6 +109,26 @@ __device__ inline void write_child(const LevelArgs& a, const Child& ch, uint32_t
     a.leaf[ch.kind - KD_LEAF0][i] = l;
     return;
   }
+  if (ch.kind == KD_PAIR) {
+    // halves sorted into the buffer other than the target, merged into the target (pad)
+    if (i + 1 >= a.caps.leaf) {
+      atomicOr(&a.ctr->error, ERR_LEAF);
+      return;
+    }
+    const uint32_t h = ch.c / 2;
+    Leaf l;
+    l.off = ch.off;
+    l.size = h;
+    l.bits = ch.hi;
+    l.from = ch.buf;
+    l.to = (uint8_t)(1 - ch.tgt);
+    l.pad = ch.tgt;
+    a.leaf[LEAF_PAIR][i] = l;
+    l.off = ch.off + h;
+    l.size = ch.c - h;
+    a.leaf[LEAF_PAIR][i + 1] = l;
+    return;
+  }
   // next-level task
   if (i >= a.caps.tasks) {
     atomicOr(&a.ctr->error, ERR_TASKS);
@@ -136,7 +161,7 @@ __device__ inline void write_child(const LevelArgs& a, const Child& ch, uint32_t
 struct Reserve {
   uint32_t cnt[KD_N];
   uint32_t base[KD_N];
-  unsigned long long st_leaf, st_copy, st_heavy, st_merge, st_over;
+  unsigned long long st_leaf, st_copy, st_heavy, st_merge, st_over, st_pair;
   uint32_t max_size, records;
 };
 
@@ -157,6 +182,7 @@ __device__ inline void reserve_global(const LevelArgs& a, Reserve* r) {
     if (r->st_heavy) atomicAdd(&c->st_heavy_records, r->st_heavy);
     if (r->st_merge) atomicAdd(&c->st_merge_records, r->st_merge);
     if (r->st_over) atomicAdd(&c->st_overflow_records, r->st_over);
+    if (r->st_pair) atomicAdd(&c->st_pair_records, r->st_pair);
     if (r->max_size) atomicMax(&c->next_max_size, r->max_size);
     if (r->records) atomicAdd(&c->next_records, r->records);
   }
@@ -165,7 +191,7 @@ __device__ inline void reserve_global(const LevelArgs& a, Reserve* r) {
 __device__ inline void reserve_init(Reserve* r) {
   if (threadIdx.x < KD_N) r->cnt[threadIdx.x] = 0;
   if (threadIdx.x == 0) {
-    r->st_leaf = r->st_copy = r->st_heavy = r->st_merge = r->st_over = 0;
+    r->st_leaf = r->st_copy = r->st_heavy = r->st_merge = r->st_over = r->st_pair = 0;
     r->max_size = 0;
     r->records = 0;
   }
@@ -186,7 +212,9 @@ __device__ inline Child plan_child(const LevelArgs& a, Reserve* r, uint64_t off,
   if (ch.kind >= 0) {
     ch.slot = reserve_local(r, ch.kind, units);
     if (ch.kind == KD_COPY) atomicAdd(&r->st_copy, (unsigned long long)c);
-    if (ch.kind >= KD_LEAF0 && ch.kind < KD_LEAF0 + LEAF_CLASSES) atomicAdd(&r->st_leaf, (unsigned long long)c);
+    if ((ch.kind >= KD_LEAF0 && ch.kind < KD_LEAF0 + LEAF_CLASSES) || ch.kind == KD_PAIR)
+      atomicAdd(&r->st_leaf, (unsigned long long)c);
+    if (ch.kind == KD_PAIR) atomicAdd(&r->st_pair, (unsigned long long)c);
     if (ch.kind == KD_TASK) {
       atomicMax(&r->max_size, c);
       atomicAdd(&r->records, c);

@@ -83,6 +83,16 @@ template <typename K, typename V>
 void launch_leaf(const Leaf* items, const uint32_t* count, uint32_t cap, uint32_t grid, int cls, Bufs<K, V> b,
                  hipStream_t s);
 
+// Paired leaves (32-bit keys without values): a bucket of cutoff < c <=
+// 2 * cutoff records is sorted as two leaves, its halves, into the buffer
+// other than its target, and the two sorted halves are then merged into the
+// target.  `halves` holds two Leaf entries per bucket (count = entries);
+// grid_leaf / grid_merge: launch grids of the two steps.  No-op for other
+// layouts (their lists stay empty).
+template <typename K, typename V>
+void launch_pairs(const Leaf* halves, const uint32_t* count, uint32_t cap, uint32_t grid_leaf, uint32_t grid_merge,
+                  Bufs<K, V> b, hipStream_t s);
+
 // Tasks left after the last recorded level of the graph form: each sorted
 // completely by one workgroup.
 template <typename K, typename V>
@@ -128,6 +138,13 @@ constexpr uint32_t dist_tile() {
 
 // Leaf classes: the largest size each class sorts, by record layout.
 constexpr int LEAF_CLASSES = 5;
+// Index of the list (and counter) of paired-leaf halves, after the classes.
+constexpr int LEAF_PAIR = LEAF_CLASSES;
+constexpr uint32_t PAIR_MAX = 32768;  // largest bucket the pair merge holds in LDS
+template <typename K, typename V>
+constexpr bool pair_leaves() {
+  return sizeof(K) == 4 && !HasVal<V>::value;
+}
 template <typename K, typename V>
 constexpr uint32_t leaf_cap(int cls) {
   return cls == 0 ? 256u
@@ -135,5 +152,14 @@ constexpr uint32_t leaf_cap(int cls) {
                               : (cls == 2 ? 4096u
                                           : (cls == 3 ? 8192u : ((sizeof(K) == 8 && HasVal<V>::value) ? 8192u : 16384u))));
 }
+
+// Largest bucket sorted as a pair (0: none): twice the base-case cutoff,
+// within what the largest leaf class and the pair merge hold.
+template <typename K, typename V>
+constexpr uint32_t pair_max(uint32_t cutoff) {
+  return pair_leaves<K, V>() ? 2u * (cutoff < leaf_cap<K, V>(LEAF_CLASSES - 1) ? cutoff : leaf_cap<K, V>(LEAF_CLASSES - 1))
+                             : 0u;
+}
+static_assert(2 * leaf_cap<uint32_t, NoVal>(LEAF_CLASSES - 1) <= PAIR_MAX, "a pair fits the merge's LDS");
 
 }  // namespace dts

@@ -130,7 +130,9 @@ def test_recursion_shape_matches_oracle(kind, wide, params):
     say(f"shape kind={kind} wide={wide} params={params}")
     rs = np.random.default_rng(5)
     k = _keys(kind, 60000, wide, rs)
-    cfg = R.Config(seed=0, key_bytes=8 if wide else 4, gamma=params["digit_bits"], cutoff=params["lds_cutoff"])
+    # 32-bit keys without values: children of up to twice the cutoff are sorted as paired leaves
+    cfg = R.Config(seed=0, key_bytes=8 if wide else 4, gamma=params["digit_bits"], cutoff=params["lds_cutoff"],
+                   pair_leaves=not wide)
     ost = R.Stats()
     ok, _ = R.dtsort(k, None, cfg, stats=ost)
     got, st = (_sort64 if wide else _sort32)(k, **params)

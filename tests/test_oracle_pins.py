@@ -246,3 +246,22 @@ def test_determinism_given_seed():
     R.dtsort(keys, None, R.Config(key_bytes=4, seed=9, gamma=4, cutoff=100), stats=a)
     R.dtsort(keys, None, R.Config(key_bytes=4, seed=9, gamma=4, cutoff=100), stats=b)
     assert a == b
+
+
+def test_pair_leaves_rule():
+    # The base case of a child subproblem grows to 2 * cutoff with pair_leaves;
+    # the output is the same stable order, and children of cutoff < n' <= 2 *
+    # cutoff are no longer distributed.
+    rs = np.random.default_rng(12)
+    keys = rs.integers(0, 2 ** 32, 60000, dtype=np.uint64).astype(np.uint32)
+    plain, paired = R.Stats(), R.Stats()
+    a, _ = R.dtsort(keys, None, R.Config(key_bytes=4, gamma=2, cutoff=10000), stats=plain)
+    b, _ = R.dtsort(keys, None, R.Config(key_bytes=4, gamma=2, cutoff=10000, pair_leaves=True), stats=paired)
+    assert (a == np.sort(keys)).all() and (b == a).all()
+    assert plain.levels == 2 and paired.levels == 1
+    assert paired.tasks == 1 and paired.base_sorted == keys.size
+    # the root itself stays a distributed subproblem
+    small = keys[:15000]
+    st = R.Stats()
+    R.dtsort(small, None, R.Config(key_bytes=4, gamma=2, cutoff=10000, pair_leaves=True), stats=st)
+    assert st.tasks >= 1

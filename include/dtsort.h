@@ -113,6 +113,11 @@ typedef struct dtsort_opts {
                              evicted); a first call records and instantiates it.  Not with LEARNED
                              mode or profile.  Errors (invalid segment offsets) are reported only
                              when stats is given, which makes the call wait for the graph. */
+  int32_t ordered_ranks;  /* keys without values: 1 = the distribution keeps equal-bucket keys in input
+                             order (as it always does for records with values), so that the recursion
+                             shape (levels, tasks, heavy keys) depends on the seed alone (Appendix A);
+                             0 (default) = unordered ranks from LDS atomics, faster.  Equal keys cannot
+                             be told apart, so the sorted output is the same either way. */
   void* workspace;        /* optional device buffer for the ping-pong partner (see dtsort_workspace_bytes) */
   size_t workspace_bytes;
   dtsort_stats* stats;    /* optional host pointer */

@@ -62,6 +62,7 @@ class Opts(C.Structure):
         ("profile", C.c_int32),
         ("tile_shape", C.c_int32),
         ("graph", C.c_int32),
+        ("ordered_ranks", C.c_int32),
         ("workspace", C.c_void_p),
         ("workspace_bytes", C.c_size_t),
         ("stats", C.POINTER(Stats)),

@@ -237,7 +237,9 @@ __device__ inline uint64_t lds_match(unsigned long long* wm, uint32_t v, bool va
   return peers;
 }
 
-enum RankMode { RANK_BALLOT = 0, RANK_LDS = 1, RANK_HYBRID = 2, RANK_PIPE = 3 };
+// RANK_ATOMIC (keys without values only): a key's place among its tile's keys
+// of the same bucket is an LDS atomic increment, in no particular order.
+enum RankMode { RANK_BALLOT = 0, RANK_LDS = 1, RANK_HYBRID = 2, RANK_PIPE = 3, RANK_ATOMIC = 4 };
 
 // Hybrid: ballots match the low 4 bits, the LDS table matches the remaining
 // high bits (a table of at most 2^(nbits-4) slots, small enough that distinct

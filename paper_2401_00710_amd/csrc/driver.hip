@@ -430,6 +430,7 @@ static int run_sort(Ctx* c, SortJob<K, V>& J, hipStream_t s, dtsort_stats* stats
   a.plain = o.mode == DTSORT_MODE_PLAIN;
   a.key_bits = J.key_bits;
   a.tile = P.tile;
+  a.ordered = o.ordered_ranks != 0;
   if (stats) std::memset(stats, 0, sizeof(*stats));
 
   int r;
@@ -749,6 +750,7 @@ static void graph_enqueue(Work& W, const GPlan& g, const SortJob<K, V>& J, const
   a.plain = J.o.mode == DTSORT_MODE_PLAIN;
   a.key_bits = J.key_bits;
   a.tile = P.tile;
+  a.ordered = J.o.ordered_ranks != 0;
   a.caps = g.caps;
   LevelCounters* dctr = (LevelCounters*)W.ctr.p;
   for (int k = 0; k <= LEAF_PAIR; ++k) a.leaf[k] = (Leaf*)W.leaf[k].p;
@@ -812,12 +814,12 @@ struct GraphKey {
   const uint64_t* seg;
   uint32_t n_seg;
   uint64_t seed;
-  int key_bits, mode, gover, tile, levels;
+  int key_bits, mode, gover, tile, levels, ordered;
   uint32_t cutoff;
   bool operator==(const GraphKey& o) const {
     return kb == o.kb && vb == o.vb && k == o.k && v == o.v && ws == o.ws && n == o.n && seg == o.seg &&
            n_seg == o.n_seg && seed == o.seed && key_bits == o.key_bits && mode == o.mode && gover == o.gover &&
-           tile == o.tile && levels == o.levels && cutoff == o.cutoff;
+           tile == o.tile && levels == o.levels && cutoff == o.cutoff && ordered == o.ordered;
   }
 };
 
@@ -859,6 +861,7 @@ static int graph_sort(Ctx* c, SortJob<K, V>& J, void* user_ws, hipStream_t s, dt
   key.mode = J.o.mode;
   key.gover = P.gover;
   key.tile = P.tile;
+  key.ordered = J.o.ordered_ranks != 0;
   key.cutoff = P.cutoff;
   const GPlan g = graph_plan(J, P);
   key.levels = g.levels;

@@ -107,16 +107,23 @@ void launch_prep(const LevelArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_unit_fill, dim3(a.grid_tasks), dim3(256), 0, s, a);
 }
 
-// Ranking mode of the scatter (tuning knob: DTSORT_RANK=ballot|lds).
+// Ranking mode of the scatter (tuning knob: DTSORT_RANK=ballot|lds|hybrid|
+// pipe|atomic; atomic applies to keys without values only).  Unset: atomic
+// for keys without values, lds otherwise.
 static int rank_mode() {
   static int m = [] {
     const char* e = getenv("DTSORT_RANK");
     if (e && e[0] == 'b') return (int)RANK_BALLOT;
     if (e && e[0] == 'h') return (int)RANK_HYBRID;
     if (e && e[0] == 'p') return (int)RANK_PIPE;
+    if (e && e[0] == 'a') return (int)RANK_ATOMIC;
     return (int)RANK_LDS;
   }();
   return m;
+}
+static bool rank_mode_forced() {
+  static bool f = getenv("DTSORT_RANK") != nullptr;
+  return f;
 }
 
 // Counter rows of the variants for digits of at most 8 bits: 2^8 light,
@@ -289,18 +296,36 @@ __global__ __launch_bounds__(256) void k_bucketscan(LevelArgs a) {
 //  4. consecutive threads write consecutive records of each bucket's run to
 //     its next free place in the bucket (global offset - tile start + index).
 // Equal buckets keep input order at every step: the scatter is stable.
+// Keys without values may take RANK_ATOMIC instead: equal keys cannot be told
+// apart and every bucket is sorted completely later (or holds one key value),
+// so the order inside a bucket cannot show in the result; the counters are
+// then one array per tile (two, alternating, each cleared a tile ahead) and
+// the LDS left over lets more workgroups share a CU.
+// Waves per SIMD the scatter is compiled for (its register budget): four for
+// 512- and 1024-thread tiles of at most 64 bytes per thread; six for the
+// unordered-rank 512-thread tile of at most 32 bytes per thread, whose LDS
+// leaves room for three workgroups per CU.
+template <int T, int ITEMS, int KB, int RANK>
+constexpr int scatter_min_waves() {
+  return (RANK == RANK_ATOMIC && T == 512 && ITEMS * KB <= 32) ? 6
+         : ((T == 512 || T == 1024) && ITEMS * KB <= 64)     ? 4
+                                                              : 1;
+}
+
 template <typename K, typename V, int T, int ITEMS, int NBMAX, int RANK>
-__global__ __launch_bounds__(T, ((T == 512 || T == 1024) && ITEMS <= 8 &&
-                                  ITEMS * sizeof(K) * (HasVal<V>::value ? 2 : 1) <= 64) ? 4 : 1) void k_scatter(LevelArgs a, Bufs<K, V> bf) {
+__global__ __launch_bounds__(T, (scatter_min_waves<T, ITEMS, (int)(sizeof(K) * (HasVal<V>::value ? 2 : 1)), RANK>())) void k_scatter(
+    LevelArgs a, Bufs<K, V> bf) {
   constexpr int WAVES = T / WAVE;
   constexpr int TILE = T * ITEMS;
   constexpr int PER = (NBMAX + T - 1) / T;  // buckets per thread in the bucket phase
   constexpr bool HV = HasVal<V>::value;
+  constexpr bool ATOM = RANK == RANK_ATOMIC;
   constexpr int GM = NBMAX <= NB8 ? 8 : GMAX;  // widest digit of this variant
   using VT = typename std::conditional<HV, V, uint32_t>::type;
   static_assert(!HV || sizeof(V) <= sizeof(K), "values are staged in the key buffer");
-  __shared__ uint32_t cnt[WAVES * NBMAX];
-  __shared__ unsigned long long mk[RANK == RANK_BALLOT ? 1 : WAVES * NBMAX];  // zeroed match tables
+  static_assert(!(ATOM && HV), "records with values need the stable ranks");
+  __shared__ uint32_t cnt[ATOM ? 2 * NBMAX : WAVES * NBMAX];
+  __shared__ unsigned long long mk[(RANK == RANK_BALLOT || ATOM) ? 1 : WAVES * NBMAX];  // zeroed match tables
   __shared__ uint32_t run_off[NBMAX];
   __shared__ int32_t gdelta[NBMAX];
   __shared__ uint32_t L[(1 << GM) + 1];
@@ -315,10 +340,13 @@ __global__ __launch_bounds__(T, ((T == 512 || T == 1024) && ITEMS <= 8 &&
   const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
   uint32_t* crow = cnt + wv * NBMAX;
   unsigned long long* wm = mk + (RANK != RANK_BALLOT ? wv * NBMAX : 0);
-  if constexpr (RANK != RANK_BALLOT) {
+  if constexpr (ATOM) {
+    for (int i = threadIdx.x; i < 2 * NBMAX; i += T) cnt[i] = 0;
+  } else if constexpr (RANK != RANK_BALLOT) {
     // the match leaves every entry zero after use: clear once
     for (int i = threadIdx.x; i < WAVES * NBMAX; i += T) mk[i] = 0ull;
   }
+  uint32_t tile_no = 0;  // tiles done by this workgroup (selects the counter array)
 
   for (uint32_t ui = blockIdx.x; ui < n_units; ui += gridDim.x) {
     const uint2 u = a.units[ui];
@@ -371,8 +399,16 @@ __global__ __launch_bounds__(T, ((T == 512 || T == 1024) && ITEMS <= 8 &&
         if constexpr (HV) vv[i] = nxv[i];
       }
       if (base + TILE < end) load_tile(base + TILE);
-      // each wave clears its own counter row (only that wave ranks with it)
-      for (uint32_t j = lane; j < nb; j += WAVE) crow[j] = 0;
+      uint32_t* tcnt = cnt + (ATOM ? (tile_no & 1u) * NBMAX : 0);  // this tile's counters (ATOM)
+      if constexpr (ATOM) {
+        // the other array was last read before the previous tile's final barrier
+        uint32_t* nxc = cnt + ((tile_no + 1u) & 1u) * NBMAX;
+        for (int j = threadIdx.x; j < NBMAX; j += T) nxc[j] = 0;
+      } else {
+        // each wave clears its own counter row (only that wave ranks with it)
+        for (uint32_t j = lane; j < nb; j += WAVE) crow[j] = 0;
+      }
+      ++tile_no;
       uint32_t bk[ITEMS];
       uint32_t pos[ITEMS];
       if constexpr (RANK == RANK_PIPE) {
@@ -392,8 +428,13 @@ __global__ __launch_bounds__(T, ((T == 512 || T == 1024) && ITEMS <= 8 &&
           bk[i] = e < tile_n ? bucket_of<K>(kk[i], pr, L, H, SPL) : 0u;
         }
       }
+      if constexpr (ATOM) {
 #pragma unroll
-      for (int i = 0; i < (RANK == RANK_PIPE ? 0 : ITEMS); ++i) {
+        for (int i = 0; i < ITEMS; ++i)
+          pos[i] = (uint32_t)striped_index<T, ITEMS>(i) < tile_n ? atomicAdd(&tcnt[bk[i]], 1u) : 0u;
+      }
+#pragma unroll
+      for (int i = 0; i < ((RANK == RANK_PIPE || ATOM) ? 0 : ITEMS); ++i) {
         const uint32_t e = (uint32_t)striped_index<T, ITEMS>(i);
         const bool valid = e < tile_n;
         const uint32_t b = bk[i];
@@ -427,8 +468,12 @@ __global__ __launch_bounds__(T, ((T == 512 || T == 1024) && ITEMS <= 8 &&
           const uint32_t b = b0 + j;
           uint32_t x = 0;
           if (b < nb) {
+            if constexpr (ATOM) {
+              x = tcnt[b];
+            } else {
 #pragma unroll
-            for (int w = 0; w < WAVES; ++w) x += cnt[w * NBMAX + b];
+              for (int w = 0; w < WAVES; ++w) x += cnt[w * NBMAX + b];
+            }
           }
           sb[j] = x;
           S += x;
@@ -441,12 +486,16 @@ __global__ __launch_bounds__(T, ((T == 512 || T == 1024) && ITEMS <= 8 &&
           if (b < nb) {
             gdelta[b] = (int32_t)run_off[b] - (int32_t)run;
             run_off[b] += sb[j];
-            uint32_t r2 = run;
+            if constexpr (ATOM) {
+              tcnt[b] = run;  // the bucket's first place in the tile
+            } else {
+              uint32_t r2 = run;
 #pragma unroll
-            for (int w = 0; w < WAVES; ++w) {
-              const uint32_t c = cnt[w * NBMAX + b];
-              cnt[w * NBMAX + b] = r2;
-              r2 += c;
+              for (int w = 0; w < WAVES; ++w) {
+                const uint32_t c = cnt[w * NBMAX + b];
+                cnt[w * NBMAX + b] = r2;
+                r2 += c;
+              }
             }
           }
           run += sb[j];
@@ -457,7 +506,7 @@ __global__ __launch_bounds__(T, ((T == 512 || T == 1024) && ITEMS <= 8 &&
       for (int i = 0; i < ITEMS; ++i) {
         const uint32_t e = (uint32_t)striped_index<T, ITEMS>(i);
         if (e < tile_n) {
-          const uint32_t p = pos[i] + crow[bk[i]];
+          const uint32_t p = pos[i] + (ATOM ? tcnt[bk[i]] : crow[bk[i]]);
           pos[i] = p;
           stage[p] = kk[i];
           stage_b[p] = (uint16_t)bk[i];
@@ -518,6 +567,21 @@ static void launch_dist_variant(const LevelArgs& a, Bufs<K, V> b, uint32_t max_c
 
 uint32_t dist_cols(int) { return 1; }
 
+// The tile shapes of the <= 8-bit variants (LevelArgs::tile).
+template <typename K, typename V, int RANK>
+static void launch_tiles(const LevelArgs& a, Bufs<K, V> b, uint32_t max_chunks, hipStream_t s, int phase) {
+  if (a.tile == 1)
+    launch_dist_variant<K, V, NB8, 256, RANK>(a, b, max_chunks, s, phase);
+  else if (a.tile == 2)
+    launch_dist_variant<K, V, NB8, 512, RANK, sizeof(K) == 4 ? 8 : 4>(a, b, max_chunks, s, phase);
+  else if (a.tile == 3)
+    launch_dist_variant<K, V, NB8, 256, RANK, sizeof(K) == 4 ? 32 : 16>(a, b, max_chunks, s, phase);
+  else if (a.tile == 4)
+    launch_dist_variant<K, V, NB8, 1024, RANK, sizeof(K) == 4 ? 8 : 4>(a, b, max_chunks, s, phase);
+  else
+    launch_dist_variant<K, V, NB8, 512, RANK>(a, b, max_chunks, s, phase);
+}
+
 // Tile shapes of the scatter for digit widths <= 8 (LevelArgs::tile):
 // 0 = 512 threads x 16 keys (x 8 for 64-bit keys), 1 = 256 x 16, 2 = 512 x 8,
 // 3 = 256 x 32 (x 16), 4 = 1024 x 8 (x 4).  Wider digits use 256 threads and
@@ -525,7 +589,14 @@ uint32_t dist_cols(int) { return 1; }
 template <typename K, typename V>
 void launch_distribute(const LevelArgs& a, Bufs<K, V> b, int g_level_max, uint32_t max_chunks, hipStream_t s,
                        int phase) {
-  const int rm = rank_mode();
+  // keys without values: unordered ranks unless ordered ones are asked for
+  // (or a mode is forced); records with values: never unordered
+  int rm = rank_mode();
+  if (HasVal<V>::value || a.ordered) {
+    if (rm == RANK_ATOMIC) rm = RANK_LDS;
+  } else if (!rank_mode_forced()) {
+    rm = RANK_ATOMIC;
+  }
   if (g_level_max <= 8) {
     if (rm == RANK_BALLOT)
       launch_dist_variant<K, V, NB8, 512, RANK_BALLOT>(a, b, max_chunks, s, phase);
@@ -533,21 +604,17 @@ void launch_distribute(const LevelArgs& a, Bufs<K, V> b, int g_level_max, uint32
       launch_dist_variant<K, V, NB8, 512, RANK_HYBRID>(a, b, max_chunks, s, phase);
     else if (rm == RANK_PIPE)
       launch_dist_variant<K, V, NB8, 512, RANK_PIPE>(a, b, max_chunks, s, phase);
-    else if (a.tile == 1)
-      launch_dist_variant<K, V, NB8, 256, RANK_LDS>(a, b, max_chunks, s, phase);
-    else if (a.tile == 2)
-      launch_dist_variant<K, V, NB8, 512, RANK_LDS, sizeof(K) == 4 ? 8 : 4>(a, b, max_chunks, s, phase);
-    else if (a.tile == 3)
-      launch_dist_variant<K, V, NB8, 256, RANK_LDS, sizeof(K) == 4 ? 32 : 16>(a, b, max_chunks, s, phase);
-    else if (a.tile == 4)
-      launch_dist_variant<K, V, NB8, 1024, RANK_LDS, sizeof(K) == 4 ? 8 : 4>(a, b, max_chunks, s, phase);
+    else if (rm == RANK_ATOMIC)
+      launch_tiles<K, V, HasVal<V>::value ? RANK_LDS : RANK_ATOMIC>(a, b, max_chunks, s, phase);
     else
-      launch_dist_variant<K, V, NB8, 512, RANK_LDS>(a, b, max_chunks, s, phase);
+      launch_tiles<K, V, RANK_LDS>(a, b, max_chunks, s, phase);
   } else {
     if (rm == RANK_BALLOT)
       launch_dist_variant<K, V, 2048, 256, RANK_BALLOT>(a, b, max_chunks, s, phase);
     else if (rm == RANK_PIPE)
       launch_dist_variant<K, V, 2048, 256, RANK_PIPE>(a, b, max_chunks, s, phase);
+    else if (rm == RANK_ATOMIC)
+      launch_dist_variant<K, V, 2048, 256, HasVal<V>::value ? RANK_LDS : RANK_ATOMIC>(a, b, max_chunks, s, phase);
     else
       launch_dist_variant<K, V, 2048, 256, RANK_LDS>(a, b, max_chunks, s, phase);
   }

@@ -39,7 +39,8 @@ struct LevelArgs {
   uint32_t leaf_max[LEAF_CLASSES_MAX];  // size limit of each leaf class
   int plain;
   int key_bits;
-  int tile;  // scatter tile shape (0..3, see launch_distribute)
+  int tile;  // scatter tile shape (0..4, see launch_distribute)
+  int ordered;  // keys without values: keep equal-bucket keys in input order (stable ranks)
   uint32_t grid_tasks;  // launch grid of the per-task kernels
   uint32_t grid_units;  // launch grid of the per-unit kernels
 };

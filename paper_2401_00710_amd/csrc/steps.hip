@@ -53,6 +53,7 @@ int plan_and_distribute(const K* keys, const V* vals, size_t n, int hi, int skip
   a.g_override = o.digit_bits;
   a.cutoff = 16384;
   a.plain = o.mode == DTSORT_MODE_PLAIN;
+  a.ordered = o.ordered_ranks != 0;
   a.key_bits = 8 * sizeof(K);
   a.n_tasks = 1;
   a.chunk = (uint32_t)chunk;

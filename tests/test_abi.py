@@ -52,7 +52,7 @@ int main(void) {
   F(dtsort_opts, seed); F(dtsort_opts, key_bits); F(dtsort_opts, mode); F(dtsort_opts, digit_bits);
   F(dtsort_opts, lds_cutoff); F(dtsort_opts, tuned); F(dtsort_opts, learned_steps);
   F(dtsort_opts, learned_batch); F(dtsort_opts, learned_lr); F(dtsort_opts, profile);
-  F(dtsort_opts, tile_shape); F(dtsort_opts, graph); F(dtsort_opts, workspace);
+  F(dtsort_opts, tile_shape); F(dtsort_opts, graph); F(dtsort_opts, ordered_ranks); F(dtsort_opts, workspace);
   F(dtsort_opts, workspace_bytes); F(dtsort_opts, stats);
   F(dtsort_stats, levels); F(dtsort_stats, overflow_records); F(dtsort_stats, learned_used);
   F(dtsort_stats, learned_ms); F(dtsort_stats, kernel_ms); F(dtsort_stats, kernel_bytes);

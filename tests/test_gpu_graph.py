@@ -81,9 +81,9 @@ def test_graph_segmented_stats_equal_eager():
     do = dev_u64(off)
     st_e, st_g = dt.Stats(), dt.Stats()
     de = dev_u32(k)
-    dt.sort_segmented(de, do, opts=dt.make_opts(stats=st_e))
+    dt.sort_segmented(de, do, opts=dt.make_opts(stats=st_e, ordered_ranks=1))
     dg = dev_u32(k)
-    dt.sort_segmented(dg, do, opts=dt.make_opts(stats=st_g, graph=1))
+    dt.sort_segmented(dg, do, opts=dt.make_opts(stats=st_g, graph=1, ordered_ranks=1))
     torch.cuda.synchronize()
     assert np.array_equal(host_u32(de), host_u32(dg))
     assert _shape(st_e) == _shape(st_g)
@@ -118,8 +118,8 @@ def test_graph_whole_array(kind):
         k = (lead | (low & (lead - np.uint64(1)))).astype(np.uint32)
     st_e, st_g = dt.Stats(), dt.Stats()
     de, dg = dev_u32(k), dev_u32(k)
-    dt.sort_u32(de, dt.make_opts(stats=st_e, seed=3))
-    dt.sort_u32(dg, dt.make_opts(stats=st_g, seed=3, graph=1))
+    dt.sort_u32(de, dt.make_opts(stats=st_e, seed=3, ordered_ranks=1))
+    dt.sort_u32(dg, dt.make_opts(stats=st_g, seed=3, graph=1, ordered_ranks=1))
     torch.cuda.synchronize()
     ref = S.stable_sort_keys(k)
     assert np.array_equal(host_u32(de), ref)

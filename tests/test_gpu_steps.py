@@ -138,11 +138,22 @@ def test_step_distribute(kind, wide, g, plain):
     h = host_u64 if wide else host_u32
     assert np.array_equal(h(ok), ek)
     assert np.array_equal(h(ov), ev)
-    # keys only
+    # keys only with ordered ranks: the oracle's order
+    o.ordered_ranks = 1
     ok2 = torch.empty_like(dk)
     st = f(dk.data_ptr(), None, n, hi, C.byref(o), ok2.data_ptr(), None, counts.ctypes.data, plan.ctypes.data,
            heavy.ctypes.data, light.ctypes.data, _stream())
     assert st == 0 and np.array_equal(h(ok2), ek)
+    # keys only with unordered ranks (the default): the same buckets, each
+    # holding the oracle's keys in some order
+    o.ordered_ranks = 0
+    ok3 = torch.empty_like(dk)
+    st = f(dk.data_ptr(), None, n, hi, C.byref(o), ok3.data_ptr(), None, counts.ctypes.data, plan.ctypes.data,
+           heavy.ctypes.data, light.ctypes.data, _stream())
+    assert st == 0 and np.array_equal(counts[:p.n_buckets], ecnt)
+    bidx = np.repeat(np.arange(p.n_buckets), ecnt.astype(np.int64))
+    got3 = h(ok3)
+    assert np.array_equal(got3[np.lexsort((got3, bidx))], ek[np.lexsort((ek, bidx))])
 
 
 @pytest.mark.parametrize("wide,vals", [(False, False), (False, True), (True, False), (True, True)])

@@ -340,6 +340,22 @@ __device__ inline __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, uint32_t byt
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
 }
 
+// 16 bytes (4 u32 or 2 u64 keys) at a 16-byte aligned offset of the resource.
+template <typename K>
+__device__ inline void buf_load16(__amdgpu_buffer_rsrc_t r, uint32_t off_bytes, K* out) {
+  typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+  const v4u v = __builtin_bit_cast(v4u, __builtin_amdgcn_raw_buffer_load_b128(r, (int)off_bytes, 0, 0));
+  if constexpr (sizeof(K) == 8) {
+    out[0] = (K)v.x | ((K)v.y << 32);
+    out[1] = (K)v.z | ((K)v.w << 32);
+  } else {
+    out[0] = v.x;
+    out[1] = v.y;
+    out[2] = v.z;
+    out[3] = v.w;
+  }
+}
+
 template <typename K>
 __device__ inline K buf_load(__amdgpu_buffer_rsrc_t r, uint32_t off_bytes) {
   if constexpr (sizeof(K) == 8) {

@@ -172,24 +172,37 @@ __global__ __launch_bounds__(T) void k_hist(LevelArgs a, const K* k0, const K* k
     const K* keys = (t.src ? k1 : k0) + t.off;
     const uint32_t beg = u.y * chunk;
     const uint32_t end = min(t.size, beg + chunk);
-    for (uint32_t base = beg; base < end; base += T * ITEMS) {
-      // loads past the end of the chunk read zero; those lanes are masked below
-      const __amdgpu_buffer_rsrc_t rk = buf_rsrc(keys + base, (min(end - base, (uint32_t)(T * ITEMS))) * sizeof(K));
+    // a short first tile up to the next 16-byte boundary; every later whole
+    // tile is then read with 16-byte loads
+    constexpr int VEC = 16 / (int)sizeof(K);  // keys per 16-byte load
+    static_assert(ITEMS % VEC == 0, "whole 16-byte loads");
+    const uint32_t mis = (uint32_t)(reinterpret_cast<uintptr_t>(keys + beg) & 15u) / (uint32_t)sizeof(K);
+    const uint32_t head = mis ? (uint32_t)VEC - mis : 0u;
+    for (uint32_t base = beg; base < end;) {
+      const uint32_t len = (base == beg && head) ? min(head, end - base) : min((uint32_t)(T * ITEMS), end - base);
+      const uint32_t lim = base + len;
+      // loads past the end of the tile read zero; those lanes are masked below
+      const __amdgpu_buffer_rsrc_t rk = buf_rsrc(keys + base, len * (uint32_t)sizeof(K));
       K kk[ITEMS];
+      if (len == (uint32_t)(T * ITEMS)) {
+        // which key lands in which register does not matter for counting
 #pragma unroll
-      for (int i = 0; i < ITEMS; ++i) kk[i] = buf_load<K>(rk, (uint32_t)(i * T + threadIdx.x) * sizeof(K));
-      // every item's bucket first: the searches (splitters, heavy keys) of
-      // different items are independent and overlap their LDS latency
+        for (int j = 0; j < ITEMS / VEC; ++j)
+          buf_load16<K>(rk, (uint32_t)(j * T + threadIdx.x) * 16u, kk + j * VEC);
+      } else {
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) kk[i] = buf_load<K>(rk, (uint32_t)(i * T + threadIdx.x) * sizeof(K));
+      }
       uint32_t bb[ITEMS];
 #pragma unroll
       for (int i = 0; i < ITEMS; ++i) {
         const uint32_t e = base + i * T + threadIdx.x;
-        bb[i] = e < end ? bucket_of<K>(kk[i], pr, L, H, SPL) : 0u;
+        bb[i] = e < lim ? bucket_of<K>(kk[i], pr, L, H, SPL) : 0u;
       }
 #pragma unroll
       for (int i = 0; i < ITEMS; ++i) {
         const uint32_t e = base + i * T + threadIdx.x;
-        const bool valid = e < end;
+        const bool valid = e < lim;
         const uint32_t b = bb[i];
         const uint64_t act = __ballot(valid);
         if (act == 0) continue;
@@ -202,6 +215,7 @@ __global__ __launch_bounds__(T) void k_hist(LevelArgs a, const K* k0, const K* k
           atomicAdd(&hw[b], 1u);
         }
       }
+      base += len;
     }
     __syncthreads();
     const uint32_t ncol = t.n_chunks * a.cols;
@@ -374,14 +388,30 @@ __global__ __launch_bounds__(T, (scatter_min_waves<T, ITEMS, (int)(sizeof(K) * (
     const uint32_t end = min(t.size, beg + chunk);
 
     // tile loads through buffer resources over the tile: places past the end
-    // read zero and are masked later
+    // read zero and are masked later.  Unordered ranks: a short first tile up
+    // to the next 16-byte boundary, then every whole tile is read with 16-byte
+    // loads (which key lands in which register does not matter then).
+    constexpr int VEC = 16 / (int)sizeof(K);
+    static_assert(!ATOM || ITEMS % VEC == 0, "whole 16-byte loads");
+    const uint32_t head =
+        ATOM ? ((uint32_t)VEC - (uint32_t)(reinterpret_cast<uintptr_t>(kin + beg) & 15u) / (uint32_t)sizeof(K)) %
+                   (uint32_t)VEC
+             : 0u;
+    auto tile_len = [&](uint32_t b0) {
+      return (b0 == beg && head) ? min(head, end - b0) : min((uint32_t)TILE, end - b0);
+    };
     K nxt[ITEMS];
     VT nxv[ITEMS];
     auto load_tile = [&](uint32_t b0) {
-      const uint32_t m = min((uint32_t)TILE, end - b0);
+      const uint32_t m = tile_len(b0);
       const __amdgpu_buffer_rsrc_t rk = buf_rsrc(kin + b0, m * (uint32_t)sizeof(K));
+      if (ATOM && m == (uint32_t)TILE) {
 #pragma unroll
-      for (int i = 0; i < ITEMS; ++i) nxt[i] = buf_load<K>(rk, (uint32_t)striped_index<T, ITEMS>(i) * sizeof(K));
+        for (int j = 0; j < ITEMS / VEC; ++j) buf_load16<K>(rk, (uint32_t)(j * T + threadIdx.x) * 16u, nxt + j * VEC);
+      } else {
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) nxt[i] = buf_load<K>(rk, (uint32_t)striped_index<T, ITEMS>(i) * sizeof(K));
+      }
       if constexpr (HV) {
         const __amdgpu_buffer_rsrc_t rv = buf_rsrc(vin + b0, m * (uint32_t)sizeof(VT));
 #pragma unroll
@@ -389,8 +419,8 @@ __global__ __launch_bounds__(T, (scatter_min_waves<T, ITEMS, (int)(sizeof(K) * (
       }
     };
     load_tile(beg);
-    for (uint32_t base = beg; base < end; base += TILE) {
-      const uint32_t tile_n = min((uint32_t)TILE, end - base);
+    for (uint32_t base = beg; base < end; base += tile_len(base)) {
+      const uint32_t tile_n = tile_len(base);
       K kk[ITEMS];
       VT vv[ITEMS];
 #pragma unroll
@@ -398,7 +428,7 @@ __global__ __launch_bounds__(T, (scatter_min_waves<T, ITEMS, (int)(sizeof(K) * (
         kk[i] = nxt[i];
         if constexpr (HV) vv[i] = nxv[i];
       }
-      if (base + TILE < end) load_tile(base + TILE);
+      if (base + tile_n < end) load_tile(base + tile_n);
       uint32_t* tcnt = cnt + (ATOM ? (tile_no & 1u) * NBMAX : 0);  // this tile's counters (ATOM)
       if constexpr (ATOM) {
         // the other array was last read before the previous tile's final barrier

@@ -60,10 +60,14 @@ constexpr int bsort_match_words() {
 // bsort_cnt_words<THREADS>() u32.  RANK_LDS needs `mk`
 // (bsort_match_words<THREADS>() zeroed u64).  On return k[]/ix[] hold the
 // sorted sequence in the striped layout and sk (si) holds it in order.
+// first_unordered (keys without indices only): the first pass ranks keys with
+// one LDS atomic each, in no particular order among equal digits.  That is
+// enough for a sort of bare keys whose input order does not matter: only the
+// passes after the first must keep the order of equal digits.
 template <typename K, int THREADS, int ITEMS, bool IDX, int RANK = RANK_BALLOT>
 __device__ void block_radix_sort(K (&k)[ITEMS], uint16_t (&ix)[ITEMS], int lo_bit, int hi_bit, K* sk,
                                  uint16_t* si, uint32_t* cnt, unsigned long long* mk = nullptr,
-                                 int n = THREADS * ITEMS) {
+                                 int n = THREADS * ITEMS, bool first_unordered = false) {
   constexpr int WAVES = THREADS / WAVE;
   constexpr int DPT = (256 + THREADS - 1) / THREADS;  // digits per thread in the scan
   const int wv = btid<THREADS>() / WAVE;
@@ -79,7 +83,16 @@ __device__ void block_radix_sort(K (&k)[ITEMS], uint16_t (&ix)[ITEMS], int lo_bi
     const uint32_t dmask = (1u << nbits) - 1u;
     uint32_t* wc = cnt + wv * 256;
     uint32_t pos[ITEMS];
-    if constexpr (RANK == RANK_PIPE) {
+    const bool unord = !IDX && first_unordered && bit == lo_bit;
+    if (unord) {
+      // one counter per digit for the whole block; a key's place among its
+      // digit's keys is an atomic increment
+#pragma unroll
+      for (int i = 0; i < ITEMS; ++i) {
+        const bool valid = row0 + i * WAVE + lane < n;
+        pos[i] = valid ? atomicAdd(&cnt[(uint32_t)(shr<K>(k[i], bit)) & dmask], 1u) : 0u;
+      }
+    } else if constexpr (RANK == RANK_PIPE) {
       uint32_t dg[ITEMS];
       bool vl[ITEMS];
 #pragma unroll
@@ -91,6 +104,7 @@ __device__ void block_radix_sort(K (&k)[ITEMS], uint16_t (&ix)[ITEMS], int lo_bi
     }
 #pragma unroll
     for (int i = 0; i < (RANK == RANK_PIPE ? 0 : ITEMS); ++i) {
+      if (unord) break;
       pos[i] = 0;
       if (row0 + i * WAVE >= n) continue;  // whole row is padding (uniform per wave)
       const bool valid = row0 + i * WAVE + lane < n;
@@ -113,6 +127,8 @@ __device__ void block_radix_sort(K (&k)[ITEMS], uint16_t (&ix)[ITEMS], int lo_bi
     }
     bsync<THREADS>();
     // exclusive offsets in (digit, wave) order; thread t owns digits [t*DPT, t*DPT+DPT)
+    // (unordered pass: one count per digit, in cnt[0..255])
+    const int nw = unord ? 1 : WAVES;
     uint32_t sd[DPT];
     uint32_t S = 0;
 #pragma unroll
@@ -120,7 +136,7 @@ __device__ void block_radix_sort(K (&k)[ITEMS], uint16_t (&ix)[ITEMS], int lo_bi
       const int d = btid<THREADS>() * DPT + j;
       uint32_t x = 0;
       if (d < 256) {
-        for (int w = 0; w < WAVES; ++w) x += cnt[w * 256 + d];
+        for (int w = 0; w < nw; ++w) x += cnt[w * 256 + d];
       }
       sd[j] = x;
       S += x;
@@ -132,7 +148,7 @@ __device__ void block_radix_sort(K (&k)[ITEMS], uint16_t (&ix)[ITEMS], int lo_bi
       const int d = btid<THREADS>() * DPT + j;
       if (d < 256) {
         uint32_t r2 = run;
-        for (int w = 0; w < WAVES; ++w) {
+        for (int w = 0; w < nw; ++w) {
           const uint32_t c = cnt[w * 256 + d];
           cnt[w * 256 + d] = r2;
           r2 += c;
@@ -141,11 +157,12 @@ __device__ void block_radix_sort(K (&k)[ITEMS], uint16_t (&ix)[ITEMS], int lo_bi
       run += sd[j];
     }
     bsync<THREADS>();
+    const uint32_t* dc = unord ? cnt : wc;  // digit bases of this key's counter row
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
       if (row0 + i * WAVE + lane < n) {
         const uint32_t d = (uint32_t)(shr<K>(k[i], bit)) & dmask;
-        const uint32_t p = pos[i] + wc[d];
+        const uint32_t p = pos[i] + dc[d];
         sk[p] = k[i];
         if constexpr (IDX) si[p] = ix[i];
       }
@@ -183,7 +200,7 @@ __device__ void block_sort_bits(K (&k)[ITEMS], uint16_t (&ix)[ITEMS], int lo_bit
   static_assert(THREADS * ITEMS / 32 <= bsort_cnt_words<THREADS>(), "run bitmap must fit in the counters");
   if (hi_bit - lo_bit <= PREFIX_BITS + 8) {
     // at most three passes: the prefix path would save at most one
-    block_radix_sort<K, THREADS, ITEMS, IDX, RANK>(k, ix, lo_bit, hi_bit, sk, si, cnt, mk, n);
+    block_radix_sort<K, THREADS, ITEMS, IDX, RANK>(k, ix, lo_bit, hi_bit, sk, si, cnt, mk, n, !IDX);
     return;
   }
   const int pb = hi_bit - PREFIX_BITS;
@@ -191,7 +208,9 @@ __device__ void block_sort_bits(K (&k)[ITEMS], uint16_t (&ix)[ITEMS], int lo_bit
   // 0: [pb, hi); if the fix-up gives way, 1: [lo, pb) and 2: [pb, hi)
   int r_lo = pb, r_hi = hi_bit;
   for (int round = 0;; ++round) {
-    block_radix_sort<K, THREADS, ITEMS, IDX, RANK>(k, ix, r_lo, r_hi, sk, si, cnt, mk, n);
+    // rounds 0 and 1 start from an order that does not matter; round 2 must
+    // keep round 1's order of equal prefixes
+    block_radix_sort<K, THREADS, ITEMS, IDX, RANK>(k, ix, r_lo, r_hi, sk, si, cnt, mk, n, !IDX && round != 2);
     if (round != 0) {
       if (round == 1) {
         r_lo = pb;

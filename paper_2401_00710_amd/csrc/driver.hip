@@ -701,13 +701,15 @@ static GPlan graph_plan(const SortJob<K, V>& J, const Params& P) {
   g.grid_tasks = pg(4, c.tasks);
   g.grid_units = pg(8, c.units);
   // sorters per compute unit by leaf class (class 0 packs four one-wave
-  // sorters in a workgroup)
-  const uint32_t per_cu[LEAF_CLASSES] = {16, 8, 4, 2, 2};
+  // sorters in a workgroup): about four times what fits at once, so that the
+  // dispatcher hands the later workgroups to whichever CUs come free (leaves
+  // differ in size; each workgroup takes a fixed stride of them)
+  const uint32_t per_cu[LEAF_CLASSES] = {64, 32, 16, 8, 8};
   for (int k = 0; k < LEAF_CLASSES; ++k) g.grid_leaf[k] = pg(per_cu[k], c.leaf);
   g.grid_pair = pair_leaves<K, V>() ? pg(1, c.leaf / 2 + 1) : 0;
   g.grid_copy = pg(4, c.copies);
-  g.grid_mpos = pg(8, c.merges);
-  g.grid_munit = pg(4, c.munits);
+  g.grid_mpos = pg(32, c.merges);
+  g.grid_munit = pg(16, c.munits);
   g.grid_spill = pg(4, c.spills);
   g.grid_finish = pg(1, c.tasks);
   return g;

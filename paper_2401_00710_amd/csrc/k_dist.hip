@@ -488,7 +488,38 @@ __global__ __launch_bounds__(T, (scatter_min_waves<T, ITEMS, (int)(sizeof(K) * (
       }
       (void)nbits;
       __syncthreads();
-      {
+      if constexpr (ATOM && NBMAX <= NB8) {
+        // one wave scans the tile's bucket counts (no block-wide scan and its
+        // barriers): lane l takes buckets [l * PB, l * PB + PB)
+        constexpr int PB = (NBMAX + WAVE - 1) / WAVE;
+        if (wv == 0) {
+          uint32_t c[PB];
+          uint32_t S = 0;
+#pragma unroll
+          for (int j = 0; j < PB; ++j) {
+            const uint32_t b = lane * PB + j;
+            c[j] = b < nb ? tcnt[b] : 0u;
+            S += c[j];
+          }
+          uint32_t x = S;
+#pragma unroll
+          for (int o = 1; o < WAVE; o <<= 1) {
+            const uint32_t y = __shfl_up(x, o, WAVE);
+            if (lane >= o) x += y;
+          }
+          uint32_t run = x - S;
+#pragma unroll
+          for (int j = 0; j < PB; ++j) {
+            const uint32_t b = lane * PB + j;
+            if (b < nb) {
+              gdelta[b] = (int32_t)run_off[b] - (int32_t)run;
+              run_off[b] += c[j];
+              tcnt[b] = run;  // the bucket's first place in the tile
+            }
+            run += c[j];
+          }
+        }
+      } else {
         // buckets [b0, b0 + PER) of this thread: totals, tile starts, wave bases
         const uint32_t b0 = threadIdx.x * PER;
         uint32_t sb[PER];

@@ -600,8 +600,11 @@ __global__ __launch_bounds__(T, (scatter_min_waves<T, ITEMS, (int)(sizeof(K) * (
           if (j < tile_n && gps[it] < t.size) vout[gps[it]] = vstage[j];
         }
       }
-      // the next tile stages into the same buffer
-      __syncthreads();
+      // the next tile stages into the same buffer.  Unordered ranks need no
+      // barrier here: the next tile's first LDS writes go to the other counter
+      // array, and it writes gdelta and the stage only after its barriers that
+      // every thread reaches once done with this tile's write-out
+      if constexpr (!ATOM) __syncthreads();
     }
   }
 }

@@ -1,0 +1,144 @@
+"""Parity at the benchmark's full sizes, in the configuration bench.py times
+(tuned parameters, the same seeded inputs).
+
+At 10^9 records the CPU oracle cannot sort the input in test time, so each
+output is checked against what holds at any size and what the oracle can
+compute one by one:
+* 32/64-bit keys: non-decreasing, the same multiset as the input (the
+  oracle's order-independent digest, taken chunk by chunk), and the exact
+  order statistics at sampled positions (numpy's selection on the input);
+* pairs with values = original index: keys non-decreasing, every output key
+  equals the input key its value points to, the values are a permutation of
+  0..n-1, and equal keys keep increasing values — together exactly the
+  unique stable order;
+* the batched workload (2e8 keys): element by element against the oracle.
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_2401_00710_amd as dt
+import workloads as W
+from oracle import sort as S
+from tests._dev import require_gpu, say
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+N = 10 ** 9
+CHUNK = 1 << 26
+
+
+def _digest(a: np.ndarray):
+    """The oracle's multiset digest, combined over chunks (count and sum add,
+    xor xors: the digest of the whole array)."""
+    c, s, x = 0, 0, 0
+    for i in range(0, a.size, CHUNK):
+        ci, si, xi = S.multiset_hash(a[i:i + CHUNK])
+        c, s, x = c + ci, (s + si) % (1 << 64), x ^ xi
+    return c, s, x
+
+
+def _nondecreasing(a: np.ndarray) -> bool:
+    for i in range(0, a.size - 1, CHUNK):
+        seg = a[i:i + CHUNK + 1]
+        if not np.all(seg[1:] >= seg[:-1]):
+            return False
+    return True
+
+
+def _host(t: torch.Tensor, dtype) -> np.ndarray:
+    return t.cpu().numpy().view(dtype)
+
+
+def _check_keys(inp: np.ndarray, out: np.ndarray, seed: int):
+    say("  sorted")
+    assert _nondecreasing(out)
+    say("  digest")
+    assert _digest(out) == _digest(inp)
+    say("  order statistics")
+    rs = np.random.default_rng(seed)
+    qs = np.unique(np.concatenate([[0, inp.size - 1, inp.size // 2], rs.integers(0, inp.size, 5)]))
+    ref = np.partition(inp, qs)[qs]
+    assert np.array_equal(out[qs], ref)
+
+
+@pytest.mark.parametrize("kind", ["uniform", "zipf1"])
+def test_full_u32(kind):
+    require_gpu()
+    say(f"full u32 {kind}: generate")
+    if kind == "uniform":
+        src = W.uniform_u32(N, seed=0, device="cuda").to(torch.int32)
+    else:
+        src = W.zipf_u32(N, 1.0, N, seed=0, device="cuda").to(torch.int32)
+    inp = _host(src, np.uint32)
+    say("  sort")
+    dt.sort_u32(src, dt.make_opts(tuned=1))
+    torch.cuda.synchronize()
+    out = _host(src, np.uint32)
+    del src
+    torch.cuda.empty_cache()
+    _check_keys(inp, out, 1)
+
+
+@pytest.mark.parametrize("kind", ["exp", "bexp"])
+def test_full_pairs_u64(kind):
+    require_gpu()
+    say(f"full pairs {kind}: generate")
+    k = (W.exponential_keys(N, 1e-5, seed=0, device="cuda") if kind == "exp"
+         else W.bit_exponential_keys(N, 0.1, seed=0, device="cuda"))
+    v = torch.arange(N, dtype=torch.int64, device="cuda")
+    inp = _host(k, np.uint64)
+    say("  sort")
+    dt.sort_pairs_u64(k, v, dt.make_opts(tuned=1))
+    torch.cuda.synchronize()
+    ok, ov = _host(k, np.uint64), _host(v, np.uint64)
+    del k, v
+    torch.cuda.empty_cache()
+    say("  sorted")
+    assert _nondecreasing(ok)
+    say("  values: a permutation")
+    seen = np.zeros(N, dtype=bool)
+    seen[ov] = True
+    assert seen.all()
+    del seen
+    say("  keys follow their values")
+    for i in range(0, N, CHUNK):
+        assert np.array_equal(ok[i:i + CHUNK], inp[ov[i:i + CHUNK]])
+    say("  stable")
+    for i in range(0, N - 1, CHUNK):
+        kk, vv = ok[i:i + CHUNK + 1], ov[i:i + CHUNK + 1]
+        eq = kk[1:] == kk[:-1]
+        assert np.all(vv[1:][eq] > vv[:-1][eq])
+
+
+def test_full_mixture_u64_learned():
+    require_gpu()
+    say("full mixture u64, learned partitioner: generate")
+    src = W.mixture_u64(N, seed=0, device="cuda")
+    inp = _host(src, np.uint64)
+    st = dt.Stats()
+    say("  sort")
+    dt.sort_u64(src, dt.make_opts(tuned=1, mode=dt.MODE_LEARNED, stats=st))
+    torch.cuda.synchronize()
+    out = _host(src, np.uint64)
+    del src
+    torch.cuda.empty_cache()
+    say(f"  learned_used={st.learned_used}")
+    _check_keys(inp, out, 2)
+
+
+@pytest.mark.parametrize("graph", [0, 1])
+def test_full_batched(graph):
+    require_gpu()
+    say(f"full batched graph={graph}: generate")
+    c = W.make_config("segmented_u32", seed=0, device="cuda")
+    keys, off = c["keys"].to(torch.int32), c["offsets"]
+    inp = _host(keys, np.uint32)
+    offs = off.cpu().numpy().view(np.uint64)
+    say("  sort")
+    dt.sort_segmented(keys, off, opts=dt.make_opts(tuned=1, graph=graph))
+    torch.cuda.synchronize()
+    out = _host(keys, np.uint32)
+    say("  oracle")
+    ek, _ = S.segmented_sort(inp, offs)
+    assert np.array_equal(out, ek)

@@ -349,6 +349,14 @@ constexpr uint32_t LEARN_HELD = 1u << 14;    // held-out sample for the balance 
 // step): draw and sort the training sample, train the CDF model, derive the
 // splitters, and let the judge keep whichever zones balance the held-out
 // sample better.  Everything stays on the device; `info` receives the verdict.
+// Zones of a learned root: at most 2^8 (255 splitters).  Finer learned zones
+// cost more than they balance: on 10^9 keys of the 64-bit mixture, 2^9 zones
+// (with 9-bit digits below) took 51 ms against 41 ms for 2^8.
+constexpr int LEARN_GAMMA = 8;
+static int learned_gamma(size_t n, int gover) {
+  return std::min(plan_gamma((uint32_t)std::min<size_t>(n, 0xFFFFFFFFu), gover), LEARN_GAMMA);
+}
+
 template <typename K, typename V>
 static int learned_root(Ctx* c, SortJob<K, V>& J, LevelArgs& a, hipStream_t s, void* info) {
   const dtsort_opts& o = J.o;
@@ -405,7 +413,7 @@ static int learned_root(Ctx* c, SortJob<K, V>& J, LevelArgs& a, hipStream_t s, v
   mlp_data<K>(samp, N, J.key_bits, x, y, s);
   mlp_train(x, y, N, o.seed, steps, batch, lr, par, m, v, part, losses, s);
   mlp_forward(par, x, N, pred, s);
-  learned_kernels_split<K>(samp, pred, N, 1u << plan_gamma((uint32_t)J.n, a.g_override), mono, spl, s);
+  learned_kernels_split<K>(samp, pred, N, 1u << learned_gamma(J.n, a.g_override), mono, spl, s);
   learned_kernels_judge<K>(a.tasks, a.tab, held, HN, spl, info, losses, steps, s);
   HIPCHK(hipGetLastError());
   return 0;
@@ -417,7 +425,12 @@ static int run_sort(Ctx* c, SortJob<K, V>& J, hipStream_t s, dtsort_stats* stats
   const size_t n = J.n;
   const dtsort_opts& o = J.o;
   const Params P = resolve_params(J);
-  const int gover = P.gover;
+  const bool learned = o.mode == DTSORT_MODE_LEARNED && !J.seg && n >= (1u << 20);
+  // a learned root takes 2^8 zones; unless the caller fixed the digit width,
+  // the levels below it take 8-bit digits too (their buckets are the learned
+  // zones' children: 10^9 keys of the 64-bit mixture sort in 41 ms with 8-bit
+  // digits below the root against 49 ms with the 9 bits tuned for sampling)
+  const int gover = (learned && o.digit_bits == 0) ? LEARN_GAMMA : P.gover;
   const uint32_t cutoff = P.cutoff;
   Work& W = c->w;
   LevelArgs a;
@@ -443,7 +456,6 @@ static int run_sort(Ctx* c, SortJob<K, V>& J, hipStream_t s, dtsort_stats* stats
   prof.s = s;
   prof.c = c;
   const double rec_bytes = (double)sizeof(K) + (HV ? (double)sizeof(V) : 0.0);
-  const bool learned = o.mode == DTSORT_MODE_LEARNED && !J.seg && n >= (1u << 20);
   hipEvent_t le0 = nullptr, le1 = nullptr;
 
   uint32_t n_tasks = 0;
@@ -515,7 +527,8 @@ static int run_sort(Ctx* c, SortJob<K, V>& J, hipStream_t s, dtsort_stats* stats
       return 0;
     }
     if ((r = ensure(W.tasks[cur], sizeof(Task), s))) return r;
-    launch_root<K>((Task*)W.tasks[cur].p, dctr, n, J.key_bits, plan_gamma((uint32_t)n, gover), s);
+    launch_root<K>((Task*)W.tasks[cur].p, dctr, n, J.key_bits,
+                   learned ? learned_gamma(n, gover) : plan_gamma((uint32_t)n, gover), s);
     n_tasks = 1;
     total = n;
     max_size = (uint32_t)n;
@@ -525,7 +538,7 @@ static int run_sort(Ctx* c, SortJob<K, V>& J, hipStream_t s, dtsort_stats* stats
   int L = 0;
   for (; n_tasks > 0; ++L) {
     if (L >= MAX_LEVELS) return fail(DTSORT_EINTERNAL, "recursion deeper than expected");
-    const int gmax = plan_gamma(max_size, gover);
+    const int gmax = (L == 0 && learned) ? learned_gamma(n, gover) : plan_gamma(max_size, gover);
     // chunk: a multiple of 8192 records aiming at ~2048 units per level (the
     // prep kernel derives the same value when it is left 0)
     uint64_t chunk = (total + 2047) / 2048;

@@ -99,7 +99,7 @@ typedef struct dtsort_opts {
   int32_t tuned;          /* 1 = take digit_bits / lds_cutoff / tile_shape from the tuning table when they are 0
                              (the file named by DTSORT_TUNE_FILE, else tune_table.txt beside the library;
                              written by the package's autotuner) */
-  int32_t learned_steps;  /* LEARNED: optimiser steps (0 = default 256) */
+  int32_t learned_steps;  /* LEARNED: optimiser steps (0 = default 128) */
   int32_t learned_batch;  /* LEARNED: batch size (0 = default 1024) */
   float learned_lr;       /* LEARNED: Adam step size (0 = default 3e-3) */
   int32_t profile;        /* 1 = time every kernel launch with HIP events into stats (adds syncs) */

@@ -122,8 +122,8 @@ def main():
     if args.once:
         return run_once(args.once, int(args.n))
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU; --gpus above 1 is not supported "
-                                   "(the sharded design is described in DESIGN.md)"}), flush=True)
+        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus above 1 is not supported "
+                                   "(the sort has no multi-GPU path)"}), flush=True)
         sys.exit(2)
 
     import numpy as np

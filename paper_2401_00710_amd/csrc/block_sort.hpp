@@ -142,7 +142,7 @@ __device__ void block_radix_sort(K (&k)[ITEMS], uint16_t (&ix)[ITEMS], int lo_bi
       S += x;
     }
     uint32_t total;
-    uint32_t run = block_excl_scan<THREADS>(S, tmp, &total);
+    uint32_t run = block_excl_scan<THREADS, false>(S, tmp, &total);  // a barrier follows before tmp is reused
 #pragma unroll
     for (int j = 0; j < DPT; ++j) {
       const int d = btid<THREADS>() * DPT + j;

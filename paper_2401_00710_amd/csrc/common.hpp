@@ -279,7 +279,9 @@ __device__ inline void rank_pipelined(const uint32_t (&v)[ITEMS], const bool (&v
 
 // Exclusive scan of one value per thread across the workgroup.  `tmp` holds
 // THREADS/64 + 1 words of LDS.  Returns the exclusive prefix; *total gets the sum.
-template <int THREADS>
+// FREE_TMP = false leaves out the final barrier that frees `tmp` for reuse:
+// for callers that pass another workgroup barrier before they scan again.
+template <int THREADS, bool FREE_TMP = true>
 __device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t* tmp, uint32_t* total) {
   constexpr int WAVES = THREADS / WAVE;
   const int lane = threadIdx.x & (WAVE - 1);
@@ -306,7 +308,7 @@ __device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t* tmp, uint32_t* 
       all += t;
     }
     *total = all;
-    __syncthreads();  // tmp is free again for the caller's next scan
+    if constexpr (FREE_TMP) __syncthreads();  // tmp is free again for the caller's next scan
     return x - v + before;
   }
 }

@@ -540,7 +540,7 @@ __global__ __launch_bounds__(T, (scatter_min_waves<T, ITEMS, (int)(sizeof(K) * (
           S += x;
         }
         uint32_t total;
-        uint32_t run = block_excl_scan<T>(S, tmp, &total);
+        uint32_t run = block_excl_scan<T, false>(S, tmp, &total);  // a barrier follows before tmp is reused
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
           const uint32_t b = b0 + j;

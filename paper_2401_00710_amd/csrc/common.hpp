@@ -377,6 +377,7 @@ struct PlanRegs {
   bool learned;
   bool top_full;  // top >= key width (no overflow test)
   bool heavy;     // the task has heavy keys (else the light id of zone z is z)
+  bool hashed;    // the heavy keys are in the workgroup's hash table (set by the kernel)
 };
 
 template <typename K>
@@ -390,15 +391,37 @@ __device__ inline PlanRegs<K> plan_regs(const Task& t) {
   p.learned = (t.flags & TF_LEARNED) != 0;
   p.top_full = t.top >= t.hi;
   p.heavy = t.n_heavy != 0;
+  p.hashed = false;
   return p;
+}
+
+// Hash table of a task's heavy keys (at most 128 of them), built in LDS by
+// the workgroups that distribute the task: HT_SLOTS words, each holding up to
+// HT_WAYS indices into the heavy-key array (one byte each, filled from the
+// low byte up, 0xFF = empty).  A key is heavy exactly when one of the
+// indices in its slot names an equal key.
+constexpr int HT_BITS = 9;
+constexpr int HT_SLOTS = 1 << HT_BITS;
+constexpr int HT_WAYS = 4;
+constexpr int HT_MAX_KEYS = 128;  // indices fit a byte below 0xFF
+
+// Slot of a key: multiplicative (Fibonacci) hashing of its (folded) 32 bits.
+template <typename K>
+__device__ inline uint32_t heavy_slot(K key) {
+  uint32_t x = (uint32_t)key;
+  if constexpr (sizeof(K) == 8) x ^= (uint32_t)((uint64_t)key >> 32);
+  return (x * 0x9E3779B1u) >> (32 - HT_BITS);
 }
 
 // Bucket id of `key`: overflow if a bit in [top, hi) is set (Section 5); else
 // the heavy id if the key is one of its zone's heavy keys; else the zone's
-// light id.  L (light ids, 2^w + 1 entries), H (heavy keys) and SPL
-// (splitters, learned root) are in LDS.
+// light id.  L (light ids, 2^w + 1 entries), H (heavy keys), SPL
+// (splitters, learned root) and HT (the heavy-key hash table, used when
+// p.hashed) are in LDS.  Without the table the heavy keys of the key's zone
+// are binary-searched.
 template <typename K>
-__device__ inline uint32_t bucket_of(K key, const PlanRegs<K>& p, const uint32_t* L, const K* H, const K* SPL) {
+__device__ inline uint32_t bucket_of(K key, const PlanRegs<K>& p, const uint32_t* L, const K* H, const K* SPL,
+                                     const uint32_t* HT) {
   K low = key & p.mask_hi;
   uint32_t z;
   if (p.learned) {
@@ -420,6 +443,19 @@ __device__ inline uint32_t bucket_of(K key, const PlanRegs<K>& p, const uint32_t
   }
   if (!p.heavy) return z;
   uint32_t lid = L[z];
+  if (p.hashed) {
+    // an equal heavy key lies in this key's zone; its bucket follows the
+    // zone's light bucket in the order of the heavy-key array
+    uint32_t w = HT[heavy_slot<K>(key)];
+#pragma unroll
+    for (int j = 0; j < HT_WAYS; ++j) {
+      const uint32_t e = w & 0xFFu;
+      if (e == 0xFFu) break;
+      if (H[e] == key) return z + 1u + e;
+      w >>= 8;
+    }
+    return lid;
+  }
   uint32_t m = L[z + 1] - lid - 1u;
   if (m) {
     uint32_t base = lid - z, lo = base, n = m;

@@ -131,8 +131,14 @@ static bool rank_mode_forced() {
 constexpr int NB8 = (nb_cap(8) + 7) / 8 * 8;
 
 // ------------------------------------------------------- table loading
+// With HT (variants of at most 8-bit digits, whose tasks have at most
+// HT_MAX_KEYS heavy keys) the heavy keys also go into the hash table HT, with
+// HC (HT_SLOTS words) counting the keys of each slot and *hfull set when a
+// slot overflows (then the keys are searched instead).  A barrier must
+// follow before the tables are read.
 template <typename K, int THREADS>
-__device__ inline void load_tables(const Task& t, const uint8_t* tab, uint32_t* L, K* H, K* SPL) {
+__device__ inline void load_tables(const Task& t, const uint8_t* tab, uint32_t* L, K* H, K* SPL, uint32_t* HT,
+                                   uint32_t* HC, uint32_t* hfull) {
   const SlotLayout sl = slot_layout(t.gamma, (t.flags & TF_LEARNED) != 0);
   const uint8_t* slot = tab + t.tab_off;
   const uint32_t* gL = (const uint32_t*)(slot + sl.light);
@@ -140,6 +146,22 @@ __device__ inline void load_tables(const Task& t, const uint8_t* tab, uint32_t* 
   const uint32_t zones = 1u << t.w;
   for (uint32_t i = threadIdx.x; i <= zones; i += THREADS) L[i] = gL[i];
   for (uint32_t i = threadIdx.x; i < t.n_heavy; i += THREADS) H[i] = (K)gH[i];
+  if (HT != nullptr && t.n_heavy != 0) {
+    for (int i = threadIdx.x; i < HT_SLOTS; i += THREADS) {
+      HT[i] = 0xFFFFFFFFu;
+      HC[i] = 0u;
+    }
+    if (threadIdx.x == 0) *hfull = 0u;
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < t.n_heavy; i += THREADS) {
+      const uint32_t s = heavy_slot<K>((K)gH[i]);
+      const uint32_t r = atomicAdd(&HC[s], 1u);
+      if (r < (uint32_t)HT_WAYS)
+        atomicAnd(&HT[s], ~(0xFFu << (8u * r)) | (i << (8u * r)));  // byte r was 0xFF
+      else
+        atomicOr(hfull, 1u);
+    }
+  }
   if (t.flags & TF_LEARNED) {
     const uint64_t* gS = (const uint64_t*)(slot + sl.spl);
     for (uint32_t i = threadIdx.x; i + 1 < zones; i += THREADS) SPL[i] = (K)gS[i];
@@ -156,6 +178,11 @@ __global__ __launch_bounds__(T) void k_hist(LevelArgs a, const K* k0, const K* k
   __shared__ uint32_t hist[WAVES * NBMAX];
   __shared__ uint32_t L[(1 << GM) + 1];
   __shared__ K H[1 << (GM - 1)];
+  constexpr bool HASH = GM == 8;  // heavy keys fit the hash table
+  static_assert(!HASH || (1 << (GM - 1)) <= HT_MAX_KEYS, "heavy indices fit a byte");
+  __shared__ uint32_t HT[HASH ? HT_SLOTS : 1];
+  __shared__ uint32_t HC[HASH ? HT_SLOTS : 1];
+  __shared__ uint32_t hfull;
   __shared__ K SPL[1 << GM];
   const uint32_t n_units = a.ctr->cur_units;
   const uint32_t chunk = a.ctr->chunk;
@@ -165,10 +192,11 @@ __global__ __launch_bounds__(T) void k_hist(LevelArgs a, const K* k0, const K* k
     const uint2 u = a.units[ui];
     const Task t = a.tasks[u.x];
     if (t.n_chunks == 0) continue;
-    load_tables<K, T>(t, a.tab, L, H, SPL);
+    load_tables<K, T>(t, a.tab, L, H, SPL, HASH ? HT : nullptr, HC, &hfull);
     for (int i = threadIdx.x; i < WAVES * NBMAX; i += T) hist[i] = 0;
     __syncthreads();
-    const PlanRegs<K> pr = plan_regs<K>(t);
+    PlanRegs<K> pr = plan_regs<K>(t);
+    pr.hashed = HASH && pr.heavy && hfull == 0u;
     const K* keys = (t.src ? k1 : k0) + t.off;
     const uint32_t beg = u.y * chunk;
     const uint32_t end = min(t.size, beg + chunk);
@@ -197,7 +225,7 @@ __global__ __launch_bounds__(T) void k_hist(LevelArgs a, const K* k0, const K* k
 #pragma unroll
       for (int i = 0; i < ITEMS; ++i) {
         const uint32_t e = base + i * T + threadIdx.x;
-        bb[i] = e < lim ? bucket_of<K>(kk[i], pr, L, H, SPL) : 0u;
+        bb[i] = e < lim ? bucket_of<K>(kk[i], pr, L, H, SPL, HT) : 0u;
       }
 #pragma unroll
       for (int i = 0; i < ITEMS; ++i) {
@@ -206,11 +234,11 @@ __global__ __launch_bounds__(T) void k_hist(LevelArgs a, const K* k0, const K* k
         const uint32_t b = bb[i];
         const uint64_t act = __ballot(valid);
         if (act == 0) continue;
-        const int first = __builtin_ctzll(act);
-        const uint32_t b0 = __shfl(b, first, WAVE);
+        // the valid lanes are a prefix of the wave, so lane 0 is one of them
+        const uint32_t b0 = __builtin_amdgcn_readfirstlane(b);
         const uint64_t same = __ballot(valid && b == b0);
         if (same == act) {
-          if (lane == first) atomicAdd(&hw[b0], (uint32_t)__popcll(act));
+          if (lane == 0) atomicAdd(&hw[b0], (uint32_t)__popcll(act));
         } else if (valid) {
           atomicAdd(&hw[b], 1u);
         }
@@ -344,6 +372,11 @@ __global__ __launch_bounds__(T, (scatter_min_waves<T, ITEMS, (int)(sizeof(K) * (
   __shared__ int32_t gdelta[NBMAX];
   __shared__ uint32_t L[(1 << GM) + 1];
   __shared__ K H[1 << (GM - 1)];
+  constexpr bool HASH = GM == 8;  // heavy keys fit the hash table
+  static_assert(!HASH || (1 << (GM - 1)) <= HT_MAX_KEYS, "heavy indices fit a byte");
+  __shared__ uint32_t HT[HASH ? HT_SLOTS : 1];
+  __shared__ uint32_t HC[HASH ? HT_SLOTS : 1];
+  __shared__ uint32_t hfull;
   __shared__ K SPL[1 << GM];
   __shared__ K stage[TILE];
   __shared__ uint16_t stage_b[TILE];
@@ -366,7 +399,7 @@ __global__ __launch_bounds__(T, (scatter_min_waves<T, ITEMS, (int)(sizeof(K) * (
     const uint2 u = a.units[ui];
     const Task t = a.tasks[u.x];
     if (t.n_chunks == 0) continue;
-    load_tables<K, T>(t, a.tab, L, H, SPL);
+    load_tables<K, T>(t, a.tab, L, H, SPL, HASH ? HT : nullptr, HC, &hfull);
     const SlotLayout sl = slot_layout(t.gamma, (t.flags & TF_LEARNED) != 0);
     const uint32_t* starts = (const uint32_t*)(a.tab + t.tab_off + sl.starts);
     const uint32_t nb = t.n_buckets;
@@ -374,7 +407,8 @@ __global__ __launch_bounds__(T, (scatter_min_waves<T, ITEMS, (int)(sizeof(K) * (
       run_off[b] = starts[b] + a.cm[t.cm_off + (uint64_t)b * t.n_chunks * a.cols + u.y];
     __syncthreads();
 
-    const PlanRegs<K> pr = plan_regs<K>(t);
+    PlanRegs<K> pr = plan_regs<K>(t);
+    pr.hashed = HASH && pr.heavy && hfull == 0u;
     const K* kin = bf.k[t.src] + t.off;
     K* kout = bf.k[1 - t.src] + t.off;
     const VT* vin = nullptr;
@@ -446,7 +480,7 @@ __global__ __launch_bounds__(T, (scatter_min_waves<T, ITEMS, (int)(sizeof(K) * (
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
           vl[i] = (uint32_t)striped_index<T, ITEMS>(i) < tile_n;
-          bk[i] = vl[i] ? bucket_of<K>(kk[i], pr, L, H, SPL) : 0u;
+          bk[i] = vl[i] ? bucket_of<K>(kk[i], pr, L, H, SPL, HT) : 0u;
         }
         rank_pipelined<ITEMS>(bk, vl, wm, crow, pos);
       }
@@ -455,7 +489,7 @@ __global__ __launch_bounds__(T, (scatter_min_waves<T, ITEMS, (int)(sizeof(K) * (
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
           const uint32_t e = (uint32_t)striped_index<T, ITEMS>(i);
-          bk[i] = e < tile_n ? bucket_of<K>(kk[i], pr, L, H, SPL) : 0u;
+          bk[i] = e < tile_n ? bucket_of<K>(kk[i], pr, L, H, SPL, HT) : 0u;
         }
       }
       if constexpr (ATOM) {

@@ -446,15 +446,27 @@ __device__ inline uint32_t bucket_of(K key, const PlanRegs<K>& p, const uint32_t
   if (p.hashed) {
     // an equal heavy key lies in this key's zone; its bucket follows the
     // zone's light bucket in the order of the heavy-key array
+    // (most slots hold at most one key: the first index is tested without a
+    // branch; its entry is read even when empty, an in-bounds LDS read)
     uint32_t w = HT[heavy_slot<K>(key)];
+    const uint32_t e0 = w & 0xFFu;
+    const K h0 = H[e0 & (HT_MAX_KEYS - 1)];
+    const bool hit0 = (e0 != 0xFFu) & (h0 == key);
+    uint32_t id = hit0 ? z + 1u + e0 : lid;
+    w >>= 8;
+    if (!hit0 && (w & 0xFFu) != 0xFFu) {
 #pragma unroll
-    for (int j = 0; j < HT_WAYS; ++j) {
-      const uint32_t e = w & 0xFFu;
-      if (e == 0xFFu) break;
-      if (H[e] == key) return z + 1u + e;
-      w >>= 8;
+      for (int j = 1; j < HT_WAYS; ++j) {
+        const uint32_t e = w & 0xFFu;
+        if (e == 0xFFu) break;
+        if (H[e] == key) {
+          id = z + 1u + e;
+          break;
+        }
+        w >>= 8;
+      }
     }
-    return lid;
+    return id;
   }
   uint32_t m = L[z + 1] - lid - 1u;
   if (m) {

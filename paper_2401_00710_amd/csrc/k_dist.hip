@@ -221,28 +221,37 @@ __global__ __launch_bounds__(T) void k_hist(LevelArgs a, const K* k0, const K* k
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) kk[i] = buf_load<K>(rk, (uint32_t)(i * T + threadIdx.x) * sizeof(K));
       }
-      uint32_t bb[ITEMS];
+      // whole tiles (the common case) without per-key bounds checks
+      auto count = [&](auto whole) {
+        constexpr bool W = decltype(whole)::value;
+        uint32_t bb[ITEMS];
 #pragma unroll
-      for (int i = 0; i < ITEMS; ++i) {
-        const uint32_t e = base + i * T + threadIdx.x;
-        bb[i] = e < lim ? bucket_of<K>(kk[i], pr, L, H, SPL, HT) : 0u;
-      }
-#pragma unroll
-      for (int i = 0; i < ITEMS; ++i) {
-        const uint32_t e = base + i * T + threadIdx.x;
-        const bool valid = e < lim;
-        const uint32_t b = bb[i];
-        const uint64_t act = __ballot(valid);
-        if (act == 0) continue;
-        // the valid lanes are a prefix of the wave, so lane 0 is one of them
-        const uint32_t b0 = __builtin_amdgcn_readfirstlane(b);
-        const uint64_t same = __ballot(valid && b == b0);
-        if (same == act) {
-          if (lane == 0) atomicAdd(&hw[b0], (uint32_t)__popcll(act));
-        } else if (valid) {
-          atomicAdd(&hw[b], 1u);
+        for (int i = 0; i < ITEMS; ++i) {
+          const uint32_t e = base + i * T + threadIdx.x;
+          bb[i] = (W || e < lim) ? bucket_of<K>(kk[i], pr, L, H, SPL, HT) : 0u;
         }
-      }
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+          const uint32_t e = base + i * T + threadIdx.x;
+          const bool valid = W || e < lim;
+          const uint32_t b = bb[i];
+          const uint64_t act = W ? ~0ull : __ballot(valid);
+          if (act == 0) continue;
+          // the valid lanes are a prefix of the wave, so lane 0 is one of
+          // them; a row of one bucket takes one atomic
+          const uint32_t b0 = __builtin_amdgcn_readfirstlane(b);
+          const uint64_t same = __ballot(valid && b == b0);
+          if (same == act) {
+            if (lane == 0) atomicAdd(&hw[b0], (uint32_t)__popcll(act));
+          } else if (valid) {
+            atomicAdd(&hw[b], 1u);
+          }
+        }
+      };
+      if (len == (uint32_t)(T * ITEMS))
+        count(std::true_type{});
+      else
+        count(std::false_type{});
       base += len;
     }
     __syncthreads();

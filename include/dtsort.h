@@ -105,7 +105,8 @@ typedef struct dtsort_opts {
   int32_t profile;        /* 1 = time every kernel launch with HIP events into stats (adds syncs) */
   int32_t tile_shape;     /* scatter tile for digits <= 8 bits: 0 = automatic, 1 = 512 threads x 16 keys
                              (x 8 for 64-bit keys), 2 = 256 x 16, 3 = 512 x 8, 4 = 256 x 32, 5 = 1024 x 8
-                             (x 4) */
+                             (x 4), 6 = 1024 x 16 for 32-bit keys without values and unordered ranks
+                             (else as 5) */
   int32_t graph;          /* 1 = device-driven schedule recorded once into a HIP graph and replayed: no
                              host read-back between levels, the call only enqueues one graph launch.
                              The graph is cached per (entry point, pointers, sizes, options) with its

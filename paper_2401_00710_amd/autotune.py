@@ -25,7 +25,7 @@ import time
 HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(HERE))
 
-TILES = (1, 2, 3, 4, 5)
+TILES = (1, 2, 3, 4, 5, 6)
 DIGITS = (8, 9, 10)
 MIN_GAIN = 0.01  # a candidate replaces the current best only when it is at least this much faster
 

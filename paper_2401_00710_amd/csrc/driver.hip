@@ -972,7 +972,7 @@ static int sort_entry(K* keys, V* vals, size_t n, const uint64_t* seg, size_t n_
   if (key_bits > kbits) return fail(DTSORT_EINVAL, "key_bits larger than the key width");
   if (o.mode < 0 || o.mode > 2) return fail(DTSORT_EINVAL, "unknown mode");
   if (o.digit_bits < 0 || o.digit_bits > GMAX) return fail(DTSORT_EINVAL, "digit_bits out of range");
-  if (o.tile_shape < 0 || o.tile_shape > 5) return fail(DTSORT_EINVAL, "tile_shape out of range");
+  if (o.tile_shape < 0 || o.tile_shape > 6) return fail(DTSORT_EINVAL, "tile_shape out of range");
   if (o.graph && (o.mode == DTSORT_MODE_LEARNED || o.profile))
     return fail(DTSORT_EINVAL, "graph mode does not combine with LEARNED mode or profiling");
   if (seg && n_seg == 0) return 0;

@@ -655,11 +655,12 @@ __global__ __launch_bounds__(T, (scatter_min_waves<T, ITEMS, (int)(sizeof(K) * (
 template <typename K, typename V, int NBMAX, int T, int RANK, int SITEMS_REQ = 0>
 static void launch_dist_variant(const LevelArgs& a, Bufs<K, V> b, uint32_t max_chunks, hipStream_t s, int phase) {
   constexpr int HITEMS = sizeof(K) == 4 ? 16 : 8;
+  constexpr int HT = T > 512 ? 512 : T;  // the histogram of 1024-thread tiles runs faster at 512
   constexpr int SITEMS = SITEMS_REQ ? SITEMS_REQ : (sizeof(K) == 4 ? 16 : 8);
   const uint32_t nu = a.grid_units;
   const uint32_t nt = a.grid_tasks;
   if (phase < 0 || phase == 0)
-    hipLaunchKernelGGL((k_hist<K, T, HITEMS, NBMAX>), dim3(nu), dim3(T), 0, s, a, (const K*)b.k[0],
+    hipLaunchKernelGGL((k_hist<K, HT, HITEMS, NBMAX>), dim3(nu), dim3(HT), 0, s, a, (const K*)b.k[0],
                        (const K*)b.k[1]);
   if (phase < 0 || phase == 1) {
     // bucket groups along y: all of them when the host knows the chunk
@@ -685,14 +686,18 @@ static void launch_tiles(const LevelArgs& a, Bufs<K, V> b, uint32_t max_chunks, 
     launch_dist_variant<K, V, NB8, 256, RANK, sizeof(K) == 4 ? 32 : 16>(a, b, max_chunks, s, phase);
   else if (a.tile == 4)
     launch_dist_variant<K, V, NB8, 1024, RANK, sizeof(K) == 4 ? 8 : 4>(a, b, max_chunks, s, phase);
+  else if (a.tile == 5)  // 16 bare 32-bit keys a thread with unordered ranks (the stable ranks' tables would not fit)
+    launch_dist_variant<K, V, NB8, 1024, RANK, (sizeof(K) == 4 && RANK == RANK_ATOMIC) ? 16 : (sizeof(K) == 4 ? 8 : 4)>(
+        a, b, max_chunks, s, phase);
   else
     launch_dist_variant<K, V, NB8, 512, RANK>(a, b, max_chunks, s, phase);
 }
 
 // Tile shapes of the scatter for digit widths <= 8 (LevelArgs::tile):
 // 0 = 512 threads x 16 keys (x 8 for 64-bit keys), 1 = 256 x 16, 2 = 512 x 8,
-// 3 = 256 x 32 (x 16), 4 = 1024 x 8 (x 4).  Wider digits use 256 threads and
-// 2048 counters.
+// 3 = 256 x 32 (x 16), 4 = 1024 x 8 (x 4), 5 = 1024 x 16 for bare 32-bit keys
+// with unordered ranks (else as 4).  Wider digits use 256 threads and 2048
+// counters.
 template <typename K, typename V>
 void launch_distribute(const LevelArgs& a, Bufs<K, V> b, int g_level_max, uint32_t max_chunks, hipStream_t s,
                        int phase) {

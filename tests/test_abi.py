@@ -104,7 +104,7 @@ def test_host_argument_checks():
     lib.dtsort_default_opts(C.byref(bad))
     bad.digit_bits = 11
     assert lib.dtsort_u32(C.c_void_p(4096), 10, C.byref(bad), None) == L.EINVAL
-    bad.digit_bits, bad.tile_shape = 0, 6
+    bad.digit_bits, bad.tile_shape = 0, 7
     assert lib.dtsort_u32(C.c_void_p(4096), 10, C.byref(bad), None) == L.EINVAL
     bad.tile_shape, bad.graph, bad.mode = 0, 1, L.MODE_LEARNED
     assert lib.dtsort_u32(C.c_void_p(4096), 10, C.byref(bad), None) == L.EINVAL
@@ -127,7 +127,7 @@ def test_tune_table_format():
         kb, vb, seg, lo, hi, g, cut, tile = v
         assert kb in (4, 8) and vb in (0, 4, 8) and seg in (0, 1)
         assert 0 <= lo <= hi <= 63
-        assert 0 <= g <= 10 and 0 <= cut <= 16384 and 0 <= tile <= 5
+        assert 0 <= g <= 10 and 0 <= cut <= 16384 and 0 <= tile <= 6
         rows.append(v)
     # every layout the entry points take has a row
     keys = {(r[0], r[1], r[2]) for r in rows}

@@ -158,7 +158,7 @@ def test_graph_rejects_learned_and_profile():
         dt.sort_u32(x, dt.make_opts(graph=1, profile=1, stats=dt.Stats()))
 
 
-@pytest.mark.parametrize("tile", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("tile", [1, 2, 3, 4, 5, 6])
 def test_tile_shapes(tile):
     require_gpu()
     say(f"tile shape {tile}")
@@ -230,3 +230,29 @@ def test_graph_finishing_step(kind, monkeypatch):
         ek, ev = S.segmented_sort(k, off, v)
         assert np.array_equal(host_u32(dk), ek)
         assert np.array_equal(host_u32(dv), ev)
+
+
+@pytest.mark.parametrize("graph", [0, 1])
+def test_tile_shape_6_other_layouts(graph):
+    """Tile 6 is 1024 x 16 only for bare 32-bit keys with unordered ranks;
+    ordered ranks, 64-bit keys and the batched form take 1024 x 8 (x 4)."""
+    require_gpu()
+    say(f"tile shape 6 layouts graph={graph}")
+    rs = np.random.default_rng(66)
+    n = 600_007
+    k = rs.integers(0, 2 ** 32, n, dtype=np.uint64).astype(np.uint32)
+    k[rs.integers(0, n, n // 4)] = 12345  # a heavy key
+    d = dev_u32(k)
+    dt.sort_u32(d, dt.make_opts(tile_shape=6, digit_bits=8, ordered_ranks=1, graph=graph))
+    k64 = rs.integers(0, 2 ** 64, n, dtype=np.uint64)
+    d64 = dev_u64(k64)
+    dt.sort_u64(d64, dt.make_opts(tile_shape=6, digit_bits=8, graph=graph))
+    off = np.array([0, 1000, 1000, 250_000, n], dtype=np.uint64)
+    ks = rs.integers(0, 2 ** 32, n, dtype=np.uint64).astype(np.uint32)
+    ds = dev_u32(ks)
+    dt.sort_segmented(ds, torch.from_numpy(off.view(np.int64)).cuda(), opts=dt.make_opts(tile_shape=6, graph=graph))
+    torch.cuda.synchronize()
+    assert np.array_equal(host_u32(d), S.stable_sort_keys(k))
+    assert np.array_equal(host_u64(d64), S.stable_sort_keys(k64))
+    ek, _ = S.segmented_sort(ks, off)
+    assert np.array_equal(host_u32(ds), ek)

@@ -175,7 +175,11 @@ template <typename K, int T, int ITEMS, int NBMAX>
 __global__ __launch_bounds__(T) void k_hist(LevelArgs a, const K* k0, const K* k1) {
   constexpr int WAVES = T / WAVE;
   constexpr int GM = NBMAX <= NB8 ? 8 : GMAX;  // widest digit of this variant
-  __shared__ uint32_t hist[WAVES * NBMAX];
+  // two counter rows per wave on the <= 8-bit variants, for even and odd
+  // lanes: lanes of one wave that count the same hot (heavy) bucket then
+  // split over two addresses
+  constexpr int HC2 = NBMAX <= NB8 ? 2 : 1;
+  __shared__ uint32_t hist[WAVES * HC2 * NBMAX];
   __shared__ uint32_t L[(1 << GM) + 1];
   __shared__ K H[1 << (GM - 1)];
   constexpr bool HASH = GM == 8;  // heavy keys fit the hash table
@@ -187,13 +191,13 @@ __global__ __launch_bounds__(T) void k_hist(LevelArgs a, const K* k0, const K* k
   const uint32_t n_units = a.ctr->cur_units;
   const uint32_t chunk = a.ctr->chunk;
   const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
-  uint32_t* hw = hist + wv * NBMAX;
+  uint32_t* hw = hist + (wv * HC2 + (HC2 == 2 ? (lane & 1) : 0)) * NBMAX;
   for (uint32_t ui = blockIdx.x; ui < n_units; ui += gridDim.x) {
     const uint2 u = a.units[ui];
     const Task t = a.tasks[u.x];
     if (t.n_chunks == 0) continue;
     load_tables<K, T>(t, a.tab, L, H, SPL, HASH ? HT : nullptr, HC, &hfull);
-    for (int i = threadIdx.x; i < WAVES * NBMAX; i += T) hist[i] = 0;
+    for (int i = threadIdx.x; i < WAVES * HC2 * NBMAX; i += T) hist[i] = 0;
     __syncthreads();
     PlanRegs<K> pr = plan_regs<K>(t);
     pr.hashed = HASH && pr.heavy && hfull == 0u;
@@ -259,7 +263,7 @@ __global__ __launch_bounds__(T) void k_hist(LevelArgs a, const K* k0, const K* k
     for (uint32_t b = threadIdx.x; b < t.n_buckets; b += T) {
       uint32_t s = 0;
 #pragma unroll
-      for (int w = 0; w < WAVES; ++w) s += hist[w * NBMAX + b];
+      for (int w = 0; w < WAVES * HC2; ++w) s += hist[w * NBMAX + b];
       a.cm[t.cm_off + (uint64_t)b * ncol + u.y] = s;
     }
     __syncthreads();

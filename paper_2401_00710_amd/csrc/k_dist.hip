@@ -129,6 +129,8 @@ static bool rank_mode_forced() {
 // Counter rows of the variants for digits of at most 8 bits: 2^8 light,
 // 2^7 heavy and one overflow bucket, rounded up to a multiple of 8.
 constexpr int NB8 = (nb_cap(8) + 7) / 8 * 8;
+// ... and of the 9-bit variant (bare keys with unordered ranks only).
+constexpr int NB9 = (nb_cap(9) + 7) / 8 * 8;
 
 // ------------------------------------------------------- table loading
 // With HT (variants of at most 8-bit digits, whose tasks have at most
@@ -174,7 +176,7 @@ __device__ inline void load_tables(const Task& t, const uint8_t* tab, uint32_t* 
 template <typename K, int T, int ITEMS, int NBMAX>
 __global__ __launch_bounds__(T) void k_hist(LevelArgs a, const K* k0, const K* k1) {
   constexpr int WAVES = T / WAVE;
-  constexpr int GM = NBMAX <= NB8 ? 8 : GMAX;  // widest digit of this variant
+  constexpr int GM = NBMAX <= NB8 ? 8 : (NBMAX <= NB9 ? 9 : GMAX);  // widest digit of this variant
   // two counter rows per wave on the <= 8-bit variants, for even and odd
   // lanes: lanes of one wave that count the same hot (heavy) bucket then
   // split over two addresses
@@ -375,7 +377,7 @@ __global__ __launch_bounds__(T, (scatter_min_waves<T, ITEMS, (int)(sizeof(K) * (
   constexpr int PER = (NBMAX + T - 1) / T;  // buckets per thread in the bucket phase
   constexpr bool HV = HasVal<V>::value;
   constexpr bool ATOM = RANK == RANK_ATOMIC;
-  constexpr int GM = NBMAX <= NB8 ? 8 : GMAX;  // widest digit of this variant
+  constexpr int GM = NBMAX <= NB8 ? 8 : (NBMAX <= NB9 ? 9 : GMAX);  // widest digit of this variant
   using VT = typename std::conditional<HV, V, uint32_t>::type;
   static_assert(!HV || sizeof(V) <= sizeof(K), "values are staged in the key buffer");
   static_assert(!(ATOM && HV), "records with values need the stable ranks");
@@ -700,7 +702,8 @@ static void launch_tiles(const LevelArgs& a, Bufs<K, V> b, uint32_t max_chunks, 
 // Tile shapes of the scatter for digit widths <= 8 (LevelArgs::tile):
 // 0 = 512 threads x 16 keys (x 8 for 64-bit keys), 1 = 256 x 16, 2 = 512 x 8,
 // 3 = 256 x 32 (x 16), 4 = 1024 x 8 (x 4), 5 = 1024 x 16 for bare 32-bit keys
-// with unordered ranks (else as 4).  Wider digits use 256 threads and 2048
+// with unordered ranks (else as 4).  9-bit digits of bare keys use 1024 x 16
+// (x 8) tiles and 776 counters; other wider digits 256 threads and 2048
 // counters.
 template <typename K, typename V>
 void launch_distribute(const LevelArgs& a, Bufs<K, V> b, int g_level_max, uint32_t max_chunks, hipStream_t s,
@@ -724,6 +727,11 @@ void launch_distribute(const LevelArgs& a, Bufs<K, V> b, int g_level_max, uint32
       launch_tiles<K, V, HasVal<V>::value ? RANK_LDS : RANK_ATOMIC>(a, b, max_chunks, s, phase);
     else
       launch_tiles<K, V, RANK_LDS>(a, b, max_chunks, s, phase);
+  } else if (g_level_max == 9 && rm == RANK_ATOMIC && !HasVal<V>::value) {
+    // 9-bit digits of bare keys: 1024-thread tiles, so that a tile still
+    // writes runs of several keys into each of its up to 769 buckets
+    if constexpr (!HasVal<V>::value)
+      launch_dist_variant<K, V, NB9, 1024, RANK_ATOMIC, sizeof(K) == 4 ? 16 : 8>(a, b, max_chunks, s, phase);
   } else {
     if (rm == RANK_BALLOT)
       launch_dist_variant<K, V, 2048, 256, RANK_BALLOT>(a, b, max_chunks, s, phase);

@@ -102,7 +102,7 @@ def tune(sizes, reps, log):
     # size classes: [lo, hi] of floor(log2 n) and the n timed for the class
     # (the cutoff matters only relative to the bucket sizes the levels leave,
     # so each class is timed at a size inside it)
-    classes = [(0, 21, sizes[0]), (22, 25, sizes[1]), (26, 28, sizes[2]), (29, 63, sizes[3])]
+    classes = [(0, 21, sizes[0]), (22, 25, sizes[1]), (26, 28, sizes[2]), (29, 29, sizes[3]), (30, 63, sizes[4])]
     plan = [(c, cl) for c in cases for cl in classes] + [((4, 0, 1), (0, 63, 0))]
     for case, (lo, hi, n) in plan:
         kb, vb, seg = case
@@ -154,8 +154,8 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=os.path.join(HERE, "tune_table.txt"))
     ap.add_argument("--report", default=None, help="JSON file with every timing")
-    ap.add_argument("--sizes", default="1048576,16777216,134217728,1073741824",
-                    help="n timed for the classes log2n <= 21, 22..25, 26..28, >= 29")
+    ap.add_argument("--sizes", default="1048576,16777216,134217728,1000000000,1073741824",
+                    help="n timed for the classes log2n <= 21, 22..25, 26..28, 29, >= 30")
     ap.add_argument("--reps", type=int, default=2)
     args = ap.parse_args()
     import torch

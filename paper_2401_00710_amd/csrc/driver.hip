@@ -348,7 +348,7 @@ constexpr uint32_t LEARN_HELD = 1u << 14;    // held-out sample for the balance 
 // Learned root plan (LEARNED mode, root task already planned by the sampling
 // step): draw and sort the training sample, train the CDF model, derive the
 // splitters, and let the judge keep whichever zones balance the held-out
-// sample better.  Everything stays on the device; `info` receives the verdict.
+// sample better.  Everything stays on the device; `info` receives the decision.
 // Zones of a learned root: at most 2^8 (255 splitters).  Finer learned zones
 // cost more than they balance: on 10^9 keys of the 64-bit mixture, 2^9 zones
 // (with 9-bit digits below) took 51 ms against 41 ms for 2^8.

@@ -118,6 +118,34 @@ def test_distributions_u64_and_pairs(kind, params):
     assert S.is_stable_by_index(gk, gv)
 
 
+@pytest.mark.parametrize("kind", DISTS)
+@pytest.mark.parametrize("wide", [False, True])
+def test_nine_bit_digits(kind, wide):
+    """9-bit digits of bare keys run on a distribution variant of their own
+    (776 counters, 1024-thread tiles); with ordered ranks they take the
+    2048-counter variant.  Both against the definition."""
+    require_gpu()
+    say(f"nine-bit digits kind={kind} wide={wide}")
+    rs = np.random.default_rng(abs(hash(("nine", kind, wide))) % 2 ** 32)
+    k = _keys(kind, 700001, wide, rs)
+    sort = _sort64 if wide else _sort32
+    for extra in (dict(), dict(ordered_ranks=1)):
+        got, _ = sort(k, digit_bits=9, **extra)
+        assert np.array_equal(got, np.sort(k)), extra
+
+
+@pytest.mark.parametrize("wide", [False, True])
+def test_nine_bit_digits_graph(wide):
+    require_gpu()
+    say(f"nine-bit digits graph wide={wide}")
+    rs = np.random.default_rng(909 + wide)
+    k = _keys("zipf", 900001, wide, rs)
+    sort = _sort64 if wide else _sort32
+    for _ in range(2):  # recorded, then replayed
+        got, _ = sort(k, digit_bits=9, graph=1)
+        assert np.array_equal(got, np.sort(k))
+
+
 @pytest.mark.parametrize("kind,wide,params", [("zipf", False, dict(digit_bits=4, lds_cutoff=200)),
                                               ("exp", True, dict(digit_bits=3, lds_cutoff=100)),
                                               ("bexp", True, dict(digit_bits=5, lds_cutoff=150)),

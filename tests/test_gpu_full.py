@@ -4,9 +4,11 @@
 At 10^9 records the CPU oracle cannot sort the input in test time, so each
 output is checked against what holds at any size and what the oracle can
 compute one by one:
-* 32/64-bit keys: non-decreasing, the same multiset as the input (the
-  oracle's order-independent digest, taken chunk by chunk), and the exact
-  order statistics at sampled positions (numpy's selection on the input);
+* 32/64-bit keys (the 64-bit mixture both with the learned partitioner and
+  with sampling, whose tuned 9-bit digits run on a variant of their own):
+  non-decreasing, the same multiset as the input (the oracle's
+  order-independent digest, taken chunk by chunk), and the exact order
+  statistics at sampled positions (numpy's selection on the input);
 * pairs with values = original index: keys non-decreasing, every output key
   equals the input key its value points to, the values are a permutation of
   0..n-1, and equal keys keep increasing values — together exactly the
@@ -111,14 +113,16 @@ def test_full_pairs_u64(kind):
         assert np.all(vv[1:][eq] > vv[:-1][eq])
 
 
-def test_full_mixture_u64_learned():
+@pytest.mark.parametrize("mode", ["learned", "sampling"])
+def test_full_mixture_u64(mode):
     require_gpu()
-    say("full mixture u64, learned partitioner: generate")
+    say(f"full mixture u64, {mode}: generate")
     src = W.mixture_u64(N, seed=0, device="cuda")
     inp = _host(src, np.uint64)
     st = dt.Stats()
     say("  sort")
-    dt.sort_u64(src, dt.make_opts(tuned=1, mode=dt.MODE_LEARNED, stats=st))
+    m = dt.MODE_LEARNED if mode == "learned" else dt.MODE_SAMPLING
+    dt.sort_u64(src, dt.make_opts(tuned=1, mode=m, stats=st))
     torch.cuda.synchronize()
     out = _host(src, np.uint64)
     del src

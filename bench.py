@@ -14,8 +14,11 @@ Prints ONE JSON line (rank 0, N=1):
   roofline   the scatter kernel (the dominant kernel): algorithmic bytes per
              launch / its average launch time, measured with HIP events in a
              profiled extra run of each input, against the 8 TB/s HBM peak
-  cpu_baseline  the CPU oracle (numpy stable sort, one core) on a bounded
-             sample of the same inputs
+  roofline_whole_sort  the whole sort: the method's algorithmic bytes (from
+             the sorts' own counters) / the measured step time, against 8 TB/s
+  cpu_baseline  the CPU oracle's multicore stable sort (all host threads it is
+             given) on a bounded sample of the same inputs; cpu_baseline_1core
+             the one-thread numpy definition
   extra      the other workloads (64-bit pairs, batched vs per-instance calls,
              learned vs sampling partitioner)
 """
@@ -90,20 +93,49 @@ def roofline_from_stats(stats, kind=3):
 
 
 def cpu_baseline(srcs, n_sample):
-    """The CPU oracle (numpy stable sort, one thread) on the first n_sample / 2
-    keys of each input, scaled to G keys/s."""
+    """The CPU oracle's multicore stable sort (libstdc++ parallel mode on every
+    host thread OpenMP is given) on the first n_sample keys of each input,
+    scaled to G keys/s."""
     import numpy as np
-    from oracle import sort as S  # the CPU oracle, timed as the reported baseline
-    half = max(1, n_sample // 2)
+    from oracle import psort  # the CPU oracle, timed as the reported baseline
+    dt, threads = 0.0, 0
+    for src in srcs.values():
+        k = src[:n_sample].cpu().numpy().view(np.uint32).copy()
+        t0 = time.perf_counter()
+        threads = psort.sort_u32_(k)
+        dt += time.perf_counter() - t0
+    cnt = n_sample * len(srcs)
+    return {"value": round(cnt / dt / 1e9, 5), "unit": "Gkeys/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {n_sample} keys of each of the {len(srcs)} inputs (parallel stable sort on "
+                      f"{threads} threads, {dt:.2f} s wall)"}
+
+
+def cpu_baseline_1core(srcs, n_sample):
+    """The CPU oracle's definition (numpy stable sort, one thread) on the first
+    n_sample keys of each input."""
+    import numpy as np
+    from oracle import sort as S  # the CPU oracle
     dt = 0.0
     for src in srcs.values():
-        k = src[:half].cpu().numpy().view(np.uint32).copy()
+        k = src[:n_sample].cpu().numpy().view(np.uint32).copy()
         t0 = time.perf_counter()
         S.stable_sort_keys(k)
         dt += time.perf_counter() - t0
-    cnt = half * len(srcs)
+    cnt = n_sample * len(srcs)
     return {"value": round(cnt / dt / 1e9, 5), "unit": "Gkeys/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {half} keys of each of the {len(srcs)} inputs (numpy stable sort, {dt:.2f} s)"}
+            "sample": f"first {n_sample} keys of each of the {len(srcs)} inputs (numpy stable sort, {dt:.2f} s)"}
+
+
+def algorithmic_bytes(st, key_bytes, rec_bytes):
+    """Bytes the method itself moves in one sort, from the sort's own counters:
+    2 s per record of every distribution (scatter read + write), of every
+    base-case sort, of every paired base case's merge, of every dovetail-merged
+    zone and of every copy between buffers; plus the histogram's read of the
+    keys of every distributed record (reported apart)."""
+    moved = 2 * rec_bytes * (st.records_distributed + st.records_leaf_sorted + st.records_pair_merged +
+                             st.records_merged + st.records_copied)
+    hist = key_bytes * st.records_distributed
+    return moved, hist
 
 
 def main():
@@ -114,7 +146,8 @@ def main():
     ap.add_argument("--n", type=float, default=1e9)
     ap.add_argument("--digit-bits", type=int, default=-1, help="-1: autotuned table; 0: the paper's rule")
     ap.add_argument("--no-extra", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=1 << 26)
+    ap.add_argument("--cpu-sample", type=int, default=1 << 27, help="keys per input for the multicore baseline")
+    ap.add_argument("--cpu-sample-1core", type=int, default=1 << 24, help="keys per input for the one-core baseline")
     ap.add_argument("--once", default=None, metavar="WORKLOAD",
                     help="for profilers: generate WORKLOAD, sort it once (tuned), print its time and exit; one of "
                          + ", ".join(ONCE))
@@ -180,23 +213,41 @@ def main():
         if ln:
             kern[kd] = {"ms": round(ms_k, 4), "GBs": round(nb / max(ms_k, 1e-9) / 1e6, 1), "launches": ln}
     alg_bytes = sum(p.kernel_bytes[i] for p in prof.values() for i in (1, 3, 5, 6, 7))
-    # practical ceiling: a plain device copy of one input (reads and writes 4 bytes per key)
+    # the whole sort against the HBM peak: the method's algorithmic bytes (from
+    # the timed sorts' own counters) over the measured step time
+    moved = sum(algorithmic_bytes(st[k], 4, 4)[0] for k in srcs)
+    hist = sum(algorithmic_bytes(st[k], 4, 4)[1] for k in srcs)
+    whole = {"bound": "hbm", "achieved": round((moved + hist) / (ms / 1e3) / 1e9, 1), "peak": HBM_PEAK_GBS,
+             "unit": "GB/s", "frac": round((moved + hist) / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+             "frac_without_hist_reads": round(moved / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+             "bytes_per_step": moved + hist, "hist_read_bytes_per_step": hist, "hist_reads_counted": True,
+             "ms_per_step": round(ms, 4),
+             "terms": "2 s x (records distributed + leaf-sorted + pair-merged + dovetail-merged + copied) "
+                      "+ key bytes x records distributed (histogram reads); s = 4 B"}
+    # practical ceiling: the library's own copy kernel (the one the sorts use
+    # for finished buckets) on the same buffers, reading and writing 4 B a key
     log("device copy")
-    cts = []
-    for _ in range(6):
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        work.copy_(srcs["uniform"])
-        e1.record()
-        torch.cuda.synchronize()
-        cts.append(e0.elapsed_time(e1))
-    copy_gbs = 2 * 4 * n / (statistics.median(cts[1:]) / 1e3) / 1e9
-    ceiling = {"device_copy_GBs": round(copy_gbs, 1),
-               "scatter_frac_of_copy": round(roof["achieved"] / copy_gbs, 4) if roof else None,
+
+    def copy_ms(fn):
+        cts = []
+        for _ in range(6):
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            cts.append(e0.elapsed_time(e1))
+        return statistics.median(cts[1:])
+    lib_copy_gbs = 2 * 4 * n / (copy_ms(lambda: dt.copy_u32(work, srcs["uniform"])) / 1e3) / 1e9
+    torch_copy_gbs = 2 * 4 * n / (copy_ms(lambda: work.copy_(srcs["uniform"])) / 1e3) / 1e9
+    ceiling = {"library_copy_kernel_GBs": round(lib_copy_gbs, 1), "torch_copy_GBs": round(torch_copy_gbs, 1),
+               "scatter_frac_of_copy": round(roof["achieved"] / lib_copy_gbs, 4) if roof else None,
+               "whole_sort_frac_of_copy": round(whole["achieved"] / lib_copy_gbs, 4),
                "sort_floor_frac": None}
     log("cpu baseline")
     cpu = cpu_baseline(srcs, min(args.cpu_sample, n))
+    cpu1 = cpu_baseline_1core(srcs, min(args.cpu_sample_1core, n))
 
     extra = {}
     if not args.no_extra:
@@ -208,7 +259,7 @@ def main():
     per_input = {k: {"ms": round(statistics.mean(v), 4), "Gkeys_s": round(n / (statistics.mean(v) / 1e3) / 1e9, 3),
                      "levels": int(st[k].levels), "heavy_keys": int(st[k].heavy_keys)} for k, v in per.items()}
     out = {
-        "metric": "G keys/s sorted at n=1e9 (plus % of HBM roofline of the dominant kernel)",
+        "metric": "G keys/s sorted at n=1e9 + % HBM roofline (dominant kernel; whole sort beside it)",
         "value": round(2 * n / (ms / 1e3) / 1e9, 3),
         "unit": "Gkeys/s",
         "n_gpus": 1,
@@ -225,7 +276,9 @@ def main():
                    "step": "one stable sort of each input (2e9 keys)", "seed": 0,
                    "parameters": "tuning table" if tuned else f"digit_bits={dbits}", "mode": "sampling"},
         "roofline": roof,
+        "roofline_whole_sort": whole,
         "cpu_baseline": cpu,
+        "cpu_baseline_1core": cpu1,
         "per_input": per_input,
         "step_ms_all": [round(t, 4) for t in times],
         "sorted_ok": ok,

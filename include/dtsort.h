@@ -88,6 +88,9 @@ typedef struct dtsort_stats {
   double kernel_ms[8];
   double kernel_bytes[8];
   uint32_t kernel_launches[8];
+  uint64_t records_pair_merged; /* records of paired base cases (32-bit keys without values): each is leaf-sorted
+                                   as part of one half (counted in records_leaf_sorted) and then written once
+                                   more by the merge of the two halves */
 } dtsort_stats;
 
 typedef struct dtsort_opts {
@@ -215,6 +218,12 @@ int dtsort_mlp_forward(const float* params, const float* x, size_t n, float* pre
  * floats) and losses[steps] (may be NULL). */
 int dtsort_mlp_train_u64(const uint64_t* sorted_keys, size_t n, uint64_t seed, int steps, int batch,
                          float lr, float* params, float* losses, void* stream);
+
+/* Plain copy of n 32-bit words from src to dst (device, not overlapping) with
+ * the copy kernel the sorts use for finished buckets; enqueued on `stream`.
+ * A measurement aid: the HBM rate this kernel reaches is the practical ceiling
+ * the sort's byte-moving kernels are compared with. */
+int dtsort_copy_u32(uint32_t* dst, const uint32_t* src, size_t n, void* stream);
 
 /* Release the per-device cache (call with no sort in flight). */
 void dtsort_release(void);

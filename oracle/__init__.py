@@ -17,6 +17,9 @@ Modules
                 Sections 3.1-3.5, plus the overflow bucket of Section 5):
                 planning and sampling, GetBucketId, the stable counting sort
                 (Appendix B), the dovetail merge (Alg. 3) and the recursion.
+``psort``       the same definition on all host cores (C++, libstdc++'s parallel
+                stable sort; built by ``build()``): the benchmark's multicore
+                CPU baseline.
 ``mlp``         the learned partitioner's 1-64-64-1 CDF model in float64:
                 forward, backward, Adam, splitter inversion, balance error.
                 Not in the paper; parity of the training trajectory is

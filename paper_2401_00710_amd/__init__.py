@@ -12,7 +12,7 @@ import ctypes as C
 from . import _lib
 from ._lib import MODE_LEARNED, MODE_PLAIN, MODE_SAMPLING, DTSortError, Opts, Stats  # noqa: F401
 
-__all__ = ["sort_u32", "sort_u64", "sort_pairs_u64", "sort_segmented", "make_opts", "Stats",
+__all__ = ["sort_u32", "sort_u64", "sort_pairs_u64", "sort_segmented", "copy_u32", "make_opts", "Stats",
            "MODE_SAMPLING", "MODE_PLAIN", "MODE_LEARNED", "DTSortError"]
 
 
@@ -90,3 +90,14 @@ def sort_segmented(keys, offsets, values=None, opts: Opts | None = None):
     _lib.check(_lib.load().dtsort_segmented(keys.data_ptr(), vp, keys.numel(), offsets.data_ptr(),
                                             offsets.numel() - 1, C.byref(o), _stream(keys)))
     return keys if values is None else (keys, values)
+
+
+def copy_u32(dst, src):
+    """dst[:] = src with the library's copy kernel (32-bit words; a measurement
+    aid for the practical HBM ceiling)."""
+    _check_tensor(dst, 4)
+    _check_tensor(src, 4)
+    if dst.numel() != src.numel():
+        raise ValueError("dst and src differ in length")
+    _lib.check(_lib.load().dtsort_copy_u32(dst.data_ptr(), src.data_ptr(), src.numel(), _stream(src)))
+    return dst

@@ -36,6 +36,7 @@ class Stats(C.Structure):
         ("kernel_ms", C.c_double * 8),
         ("kernel_bytes", C.c_double * 8),
         ("kernel_launches", C.c_uint32 * 8),
+        ("records_pair_merged", C.c_uint64),
     ]
 
     KINDS = ("plan", "hist", "scan", "scatter", "children", "leaf", "copy", "merge")
@@ -89,6 +90,7 @@ _SIGS = {
     "dtsort_mlp_loss_grad": (_I, [_P, _P, _P, _Z, _P, _P, _P]),
     "dtsort_mlp_forward": (_I, [_P, _P, _Z, _P, _P]),
     "dtsort_mlp_train_u64": (_I, [_P, _Z, C.c_uint64, _I, _I, C.c_float, _P, _P, _P]),
+    "dtsort_copy_u32": (_I, [_P, _P, _Z, _P]),
     "dtsort_release": (None, []),
     "dtsort_last_error": (C.c_char_p, []),
     "dtsort_strerror": (C.c_char_p, [_I]),

@@ -131,6 +131,7 @@ struct LevelCounters {
 enum ErrBits : uint32_t {
   ERR_TASKS = 1, ERR_LEAF = 2, ERR_COPY = 4, ERR_MERGE = 8, ERR_UNITS = 16, ERR_CM = 32, ERR_TAB = 64,
   ERR_SEGMENTS = 128, ERR_MUNITS = 256, ERR_SPILL = 512,
+  ERR_SCATTER = 1024,  // a scattered record fell outside its task (the counts were inconsistent)
 };
 
 // Capacities of the output lists the child-planning step appends to.

@@ -63,6 +63,7 @@ struct Ctx {
   int device = -1;
   Work w;
   DevBuf lrn;
+  DevBuf copy_items;  // item list of dtsort_copy_u32
   LevelCounters* h_ctr = nullptr;  // pinned
   void* h_stage = nullptr;         // pinned staging
   hipEvent_t done = nullptr;
@@ -332,6 +333,7 @@ static void add_stats(dtsort_stats* st, const LevelCounters& h, bool level) {
   }
   for (int k = 0; k <= LEAF_PAIR; ++k) st->leaf_sorts += h.leaf[k];
   st->records_leaf_sorted += h.st_leaf_records;
+  st->records_pair_merged += h.st_pair_records;
 }
 
 struct LearnedInfoH {
@@ -730,28 +732,36 @@ static GPlan graph_plan(const SortJob<K, V>& J, const Params& P) {
   return g;
 }
 
-template <typename K, typename V>
-static int graph_alloc(Work& W, const GPlan& g, hipStream_t s) {
+// Gives every buffer of the graph-form schedule its size through `place`
+// (an allocation, or a place in a caller's region); W.lv must already hold
+// g.levels entries.
+template <typename Place>
+static int graph_buffers(Work& W, const GPlan& g, Place&& place) {
   int r;
   const Caps& c = g.caps;
-  if ((r = ensure(W.ctr, sizeof(LevelCounters) * (g.levels + 1), s))) return r;
+  if ((r = place(W.ctr, sizeof(LevelCounters) * (g.levels + 1)))) return r;
   for (auto& b : W.tasks)
-    if ((r = ensure(b, sizeof(Task) * (size_t)c.tasks, s))) return r;
-  if ((r = ensure(W.units, sizeof(uint2) * (size_t)c.units, s))) return r;
-  if ((r = ensure(W.cm, 4 * c.cm, s))) return r;
+    if ((r = place(b, sizeof(Task) * (size_t)c.tasks))) return r;
+  if ((r = place(W.units, sizeof(uint2) * (size_t)c.units))) return r;
+  if ((r = place(W.cm, 4 * c.cm))) return r;
   for (auto& b : W.leaf)
-    if ((r = ensure(b, sizeof(Leaf) * (size_t)c.leaf, s))) return r;
-  if ((r = ensure(W.copies, sizeof(Leaf) * (size_t)c.copies, s))) return r;
-  W.lv.resize(g.levels);
+    if ((r = place(b, sizeof(Leaf) * (size_t)c.leaf))) return r;
+  if ((r = place(W.copies, sizeof(Leaf) * (size_t)c.copies))) return r;
   for (int L = 0; L < g.levels; ++L) {
     LevelKeep& K_ = W.lv[L];
-    if ((r = ensure(K_.tab, g.tab_bytes, s))) return r;
-    if ((r = ensure(K_.merges, sizeof(Merge) * (size_t)c.merges, s))) return r;
-    if ((r = ensure(K_.munits, sizeof(uint2) * (size_t)c.munits, s))) return r;
-    if ((r = ensure(K_.spills, sizeof(Leaf) * (size_t)c.spills, s))) return r;
+    if ((r = place(K_.tab, g.tab_bytes))) return r;
+    if ((r = place(K_.merges, sizeof(Merge) * (size_t)c.merges))) return r;
+    if ((r = place(K_.munits, sizeof(uint2) * (size_t)c.munits))) return r;
+    if ((r = place(K_.spills, sizeof(Leaf) * (size_t)c.spills))) return r;
     K_.caps = c;
   }
   return 0;
+}
+
+template <typename K, typename V>
+static int graph_alloc(Work& W, const GPlan& g, hipStream_t s) {
+  W.lv.resize(g.levels);
+  return graph_buffers(W, g, [&](DevBuf& b, size_t bytes) { return ensure(b, bytes, s); });
 }
 
 // Enqueue the whole schedule on `s` (recordable: kernels only).
@@ -1058,9 +1068,50 @@ int dtsort_segmented(uint32_t* keys, uint32_t* values, size_t n_total, const uin
   return sort_entry<uint32_t, NoVal>(keys, (NoVal*)nullptr, n_total, seg_offsets, n_segments, opts, stream);
 }
 
+int dtsort_copy_u32(uint32_t* dst, const uint32_t* src, size_t n, void* stream) {
+  g_err.clear();
+  if (n == 0) return DTSORT_OK;
+  if (!dst || !src) return fail(DTSORT_EINVAL, "NULL pointer");
+  if (n >= (1ull << 32)) return fail(DTSORT_EINVAL, "n must be below 2^32");
+  if ((const char*)dst < (const char*)(src + n) && (const char*)src < (const char*)(dst + n))
+    return fail(DTSORT_EINVAL, "src and dst overlap");
+  hipStream_t s = (hipStream_t)stream;
+  Ctx* c;
+  int r;
+  if ((r = get_ctx(&c))) return r;
+  std::lock_guard<std::mutex> lk(g_mu);
+  // items of 2^20 words, as the sorts cut their copies
+  constexpr uint32_t PIECE = 1u << 20;
+  const uint32_t items = (uint32_t)(n / PIECE + (n % PIECE != 0 ? 1 : 0));
+  const size_t bytes = sizeof(Leaf) * items + 64;
+  if ((r = ensure(c->copy_items, bytes, s))) return r;
+  HIPCHK(hipStreamSynchronize(s));  // the pinned staging area is reused
+  if (bytes > (1u << 16)) return fail(DTSORT_EINVAL, "n too large for one call");
+  Leaf* hl = (Leaf*)c->h_stage;
+  for (uint32_t i = 0; i < items; ++i) {
+    hl[i].off = (uint64_t)i * PIECE;
+    hl[i].size = (uint32_t)std::min<uint64_t>(PIECE, n - (uint64_t)i * PIECE);
+    hl[i].bits = 0;
+    hl[i].from = 0;
+    hl[i].to = 1;
+    hl[i].pad = 0;
+  }
+  uint32_t* cnt = (uint32_t*)((char*)c->h_stage + sizeof(Leaf) * items);
+  *cnt = items;
+  HIPCHK(hipMemcpyAsync(c->copy_items.p, hl, sizeof(Leaf) * items + 4, hipMemcpyHostToDevice, s));
+  Bufs<uint32_t, NoVal> b;
+  b.k[0] = const_cast<uint32_t*>(src);
+  b.k[1] = dst;
+  launch_copy<uint32_t, NoVal>((const Leaf*)c->copy_items.p,
+                               (const uint32_t*)((char*)c->copy_items.p + sizeof(Leaf) * items), items, items, b, s);
+  HIPCHK(hipGetLastError());
+  return DTSORT_OK;
+}
+
 static void free_ctx(Ctx* c) {
   free_work(c->w);
   free_buf(c->lrn);
+  free_buf(c->copy_items);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   for (GraphEntry* e : c->graphs) free_graph(e);
   c->graphs.clear();

@@ -54,7 +54,7 @@ __global__ __launch_bounds__(1024) void k_prep(LevelArgs a) {
     uint32_t nch = 0, cme = 0;
     if (ti < n_tasks) {
       const Task& t = a.tasks[ti];
-      nch = (t.size + chunk - 1) / chunk;
+      nch = t.size / chunk + (t.size % chunk != 0u ? 1u : 0u);  // no wrap for sizes near 2^32
       cme = nch * a.cols * (uint32_t)nb_cap(t.gamma);
     }
     uint32_t tot_u, tot_c;
@@ -205,7 +205,7 @@ __global__ __launch_bounds__(T) void k_hist(LevelArgs a, const K* k0, const K* k
     pr.hashed = HASH && pr.heavy && hfull == 0u;
     const K* keys = (t.src ? k1 : k0) + t.off;
     const uint32_t beg = u.y * chunk;
-    const uint32_t end = min(t.size, beg + chunk);
+    const uint32_t end = beg + min(chunk, t.size - beg);  // no wrap for sizes near 2^32
     // a short first tile up to the next 16-byte boundary; every later whole
     // tile is then read with 16-byte loads
     constexpr int VEC = 16 / (int)sizeof(K);  // keys per 16-byte load
@@ -214,7 +214,6 @@ __global__ __launch_bounds__(T) void k_hist(LevelArgs a, const K* k0, const K* k
     const uint32_t head = mis ? (uint32_t)VEC - mis : 0u;
     for (uint32_t base = beg; base < end;) {
       const uint32_t len = (base == beg && head) ? min(head, end - base) : min((uint32_t)(T * ITEMS), end - base);
-      const uint32_t lim = base + len;
       // loads past the end of the tile read zero; those lanes are masked below
       const __amdgpu_buffer_rsrc_t rk = buf_rsrc(keys + base, len * (uint32_t)sizeof(K));
       K kk[ITEMS];
@@ -233,13 +232,13 @@ __global__ __launch_bounds__(T) void k_hist(LevelArgs a, const K* k0, const K* k
         uint32_t bb[ITEMS];
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
-          const uint32_t e = base + i * T + threadIdx.x;
-          bb[i] = (W || e < lim) ? bucket_of<K>(kk[i], pr, L, H, SPL, HT) : 0u;
+          const uint32_t e = i * T + threadIdx.x;  // place in the tile
+          bb[i] = (W || e < len) ? bucket_of<K>(kk[i], pr, L, H, SPL, HT) : 0u;
         }
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
-          const uint32_t e = base + i * T + threadIdx.x;
-          const bool valid = W || e < lim;
+          const uint32_t e = i * T + threadIdx.x;
+          const bool valid = W || e < len;
           const uint32_t b = bb[i];
           const uint64_t act = W ? ~0ull : __ballot(valid);
           if (act == 0) continue;
@@ -384,7 +383,7 @@ __global__ __launch_bounds__(T, (scatter_min_waves<T, ITEMS, (int)(sizeof(K) * (
   __shared__ uint32_t cnt[ATOM ? 2 * NBMAX : WAVES * NBMAX];
   __shared__ unsigned long long mk[(RANK == RANK_BALLOT || ATOM) ? 1 : WAVES * NBMAX];  // zeroed match tables
   __shared__ uint32_t run_off[NBMAX];
-  __shared__ int32_t gdelta[NBMAX];
+  __shared__ uint32_t gdelta[NBMAX];  // bucket's global place minus its tile place (mod 2^32)
   __shared__ uint32_t L[(1 << GM) + 1];
   __shared__ K H[1 << (GM - 1)];
   constexpr bool HASH = GM == 8;  // heavy keys fit the hash table
@@ -434,7 +433,7 @@ __global__ __launch_bounds__(T, (scatter_min_waves<T, ITEMS, (int)(sizeof(K) * (
     }
     const int nbits = nb > 1 ? 32 - __builtin_clz(nb - 1) : 1;
     const uint32_t beg = u.y * chunk;
-    const uint32_t end = min(t.size, beg + chunk);
+    const uint32_t end = beg + min(chunk, t.size - beg);  // no wrap for sizes near 2^32
 
     // tile loads through buffer resources over the tile: places past the end
     // read zero and are masked later.  Unordered ranks: a short first tile up
@@ -561,7 +560,7 @@ __global__ __launch_bounds__(T, (scatter_min_waves<T, ITEMS, (int)(sizeof(K) * (
           for (int j = 0; j < PB; ++j) {
             const uint32_t b = lane * PB + j;
             if (b < nb) {
-              gdelta[b] = (int32_t)run_off[b] - (int32_t)run;
+              gdelta[b] = run_off[b] - run;
               run_off[b] += c[j];
               tcnt[b] = run;  // the bucket's first place in the tile
             }
@@ -594,7 +593,7 @@ __global__ __launch_bounds__(T, (scatter_min_waves<T, ITEMS, (int)(sizeof(K) * (
         for (int j = 0; j < PER; ++j) {
           const uint32_t b = b0 + j;
           if (b < nb) {
-            gdelta[b] = (int32_t)run_off[b] - (int32_t)run;
+            gdelta[b] = run_off[b] - run;
             run_off[b] += sb[j];
             if constexpr (ATOM) {
               tcnt[b] = run;  // the bucket's first place in the tile
@@ -629,8 +628,13 @@ __global__ __launch_bounds__(T, (scatter_min_waves<T, ITEMS, (int)(sizeof(K) * (
         const uint32_t j = threadIdx.x + it * T;
         uint32_t gp = 0xFFFFFFFFu;
         if (j < tile_n) {
-          gp = (uint32_t)(gdelta[stage_b[j]] + (int32_t)j);
-          if (gp < t.size) kout[gp] = stage[j];
+          // unsigned: the bucket's run starts at or after the keys of earlier
+          // buckets, so the sum is the place in [0, t.size) for any size < 2^32
+          gp = gdelta[stage_b[j]] + j;
+          if (gp < t.size)
+            kout[gp] = stage[j];
+          else
+            atomicOr(&a.ctr->error, ERR_SCATTER);
         }
         if constexpr (HV) gps[it] = gp;
       }

@@ -18,6 +18,8 @@
 namespace dts {
 
 constexpr uint32_t COPY_PIECE = 1u << 20;   // records per copy item
+// Copy items of c records (no wrap-around for c near 2^32).
+__device__ __host__ inline uint32_t pieces_of(uint32_t c) { return c / COPY_PIECE + (c % COPY_PIECE != 0u ? 1u : 0u); }
 constexpr uint32_t MERGE_TILE = 4096;       // outputs per gather unit
 
 // Kinds of work a finished distribution hands on (one output list each).
@@ -38,7 +40,7 @@ __device__ inline int child_kind(const LevelArgs& a, uint32_t c, int hi, int buf
   if (c == 0) return -1;
   if (c == 1 || hi == 0) {  // finished: one record or all keys equal
     if (buf == tgt) return -1;
-    *units = (c + COPY_PIECE - 1) / COPY_PIECE;
+    *units = pieces_of(c);
     return KD_COPY;
   }
   if (c <= a.cutoff) {
@@ -78,7 +80,7 @@ __device__ inline void write_child(const LevelArgs& a, const Child& ch, uint32_t
   if (ch.kind < 0) return;
   const uint32_t i = base + ch.slot;
   if (ch.kind == KD_COPY) {
-    for (uint32_t p = 0, k = 0; p < ch.c; p += COPY_PIECE, ++k) {
+    for (uint32_t p = 0, k = 0; k < pieces_of(ch.c); p += COPY_PIECE, ++k) {
       if (i + k >= a.caps.copies) {
         atomicOr(&a.ctr->error, ERR_COPY);
         return;
@@ -300,7 +302,7 @@ __global__ __launch_bounds__(256) void k_children(LevelArgs a) {
       g.hbase = lid - z;
       g.bstart = lid;
       g.zone_rel = s0;
-      g.n_units = (zsize + MERGE_TILE - 1) / MERGE_TILE;
+      g.n_units = zsize / MERGE_TILE + (zsize % MERGE_TILE != 0u ? 1u : 0u);
       g.b0_buf = (uint8_t)ctgt;
       g.hv_buf = (uint8_t)dst;
       g.out_buf = (uint8_t)t.tgt;
@@ -308,7 +310,7 @@ __global__ __launch_bounds__(256) void k_children(LevelArgs a) {
       spieces[k] = 0;
       if (HV && dst == t.tgt && zsize > c0) {
         // heavy values would be overwritten by the gather: copy them to src first
-        spieces[k] = (zsize - c0 + COPY_PIECE - 1) / COPY_PIECE;
+        spieces[k] = pieces_of(zsize - c0);
         g.hv_buf = (uint8_t)t.src;
         sslot[k] = reserve_local(&r, KD_SPILL, spieces[k]);
         atomicAdd(&r.st_copy, (unsigned long long)(zsize - c0));
@@ -360,7 +362,7 @@ __global__ __launch_bounds__(256) void k_children(LevelArgs a) {
     if (spieces[k]) {
       const uint32_t si = r.base[KD_SPILL] + sslot[k];
       const uint32_t zsize = g.n_units ? st[g.bstart + g.m + 1] - st[g.bstart] : 0;
-      for (uint32_t p = g.b0, q = 0; p < zsize; p += COPY_PIECE, ++q) {
+      for (uint32_t p = g.b0, q = 0; q < pieces_of(zsize - g.b0); p += COPY_PIECE, ++q) {
         if (si + q >= a.caps.spills) {
           atomicOr(&a.ctr->error, ERR_SPILL);
           break;
@@ -504,10 +506,11 @@ __global__ __launch_bounds__(256) void k_merge_gather(const Merge* m, const uint
   block_excl_scan_array<256>(PRE, (int)mg.m, tmp);
   const uint32_t zsize = st[mg.bstart + mg.m + 1] - st[mg.bstart];
   const uint32_t q0 = u.y * MERGE_TILE;
-  const uint32_t q1 = min(zsize, q0 + MERGE_TILE);
+  const uint32_t qn = min((uint32_t)MERGE_TILE, zsize - q0);  // outputs of this unit
   const K* lk = bf.k[mg.b0_buf] + mg.zone_off;
   K* ok = bf.k[mg.out_buf] + mg.zone_off;
-  for (uint32_t q = q0 + threadIdx.x; q < q1; q += 256) {
+  for (uint32_t qi = threadIdx.x; qi < qn; qi += 256) {
+    const uint32_t q = q0 + qi;
     // largest i with P[i] <= q
     uint32_t lo = 0, n = mg.m;
     while (n > 0) {

@@ -41,6 +41,9 @@ def test_binding_matches_header():
 
 
 def _c_layout():
+    # every field of the ctypes mirrors, so that a field added on one side only fails here
+    fields = [f"  F(dtsort_opts, {n});" for n, _ in L.Opts._fields_]
+    fields += [f"  F(dtsort_stats, {n});" for n, _ in L.Stats._fields_]
     src = r'''
 #include <stddef.h>
 #include <stdio.h>
@@ -49,14 +52,7 @@ def _c_layout():
 int main(void) {
   printf("sizeof opts %zu\n", sizeof(dtsort_opts));
   printf("sizeof stats %zu\n", sizeof(dtsort_stats));
-  F(dtsort_opts, seed); F(dtsort_opts, key_bits); F(dtsort_opts, mode); F(dtsort_opts, digit_bits);
-  F(dtsort_opts, lds_cutoff); F(dtsort_opts, tuned); F(dtsort_opts, learned_steps);
-  F(dtsort_opts, learned_batch); F(dtsort_opts, learned_lr); F(dtsort_opts, profile);
-  F(dtsort_opts, tile_shape); F(dtsort_opts, graph); F(dtsort_opts, ordered_ranks); F(dtsort_opts, workspace);
-  F(dtsort_opts, workspace_bytes); F(dtsort_opts, stats);
-  F(dtsort_stats, levels); F(dtsort_stats, overflow_records); F(dtsort_stats, learned_used);
-  F(dtsort_stats, learned_ms); F(dtsort_stats, kernel_ms); F(dtsort_stats, kernel_bytes);
-  F(dtsort_stats, kernel_launches);
+''' + "\n".join(fields) + r'''
   return 0;
 }
 '''

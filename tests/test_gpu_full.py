@@ -82,17 +82,43 @@ def test_full_u32(kind):
     _check_keys(inp, out, 1)
 
 
-@pytest.mark.parametrize("kind", ["exp", "bexp"])
-def test_full_pairs_u64(kind):
+@pytest.mark.timeout(900)
+def test_full_u32_beyond_2p31():
+    """2^31 + 3 keys: task sizes, chunk ends and scatter places above 2^31
+    (unsigned 32-bit arithmetic throughout; the interface admits n < 2^32)."""
     require_gpu()
-    say(f"full pairs {kind}: generate")
+    n = (1 << 31) + 3
+    say(f"u32 n={n}: generate")
+    src = W.uniform_u32(n, seed=5, device="cuda").to(torch.int32)
+    inp = _host(src, np.uint32)
+    say("  sort")
+    st = dt.Stats()
+    dt.sort_u32(src, dt.make_opts(tuned=1, stats=st))
+    torch.cuda.synchronize()
+    out = _host(src, np.uint32)
+    del src
+    torch.cuda.empty_cache()
+    assert st.records_distributed >= n
+    _check_keys(inp, out, 3)
+
+
+@pytest.mark.parametrize("kind,mode", [("exp", "sampling"), ("bexp", "sampling"), ("bexp", "learned")])
+def test_full_pairs_u64(kind, mode):
+    require_gpu()
+    say(f"full pairs {kind} {mode}: generate")
     k = (W.exponential_keys(N, 1e-5, seed=0, device="cuda") if kind == "exp"
          else W.bit_exponential_keys(N, 0.1, seed=0, device="cuda"))
     v = torch.arange(N, dtype=torch.int64, device="cuda")
     inp = _host(k, np.uint64)
     say("  sort")
-    dt.sort_pairs_u64(k, v, dt.make_opts(tuned=1))
+    st = dt.Stats()
+    m = dt.MODE_LEARNED if mode == "learned" else dt.MODE_SAMPLING
+    dt.sort_pairs_u64(k, v, dt.make_opts(tuned=1, mode=m, stats=st))
     torch.cuda.synchronize()
+    if mode == "learned":
+        # the benchmark reports this configuration with the model's zones in use
+        say(f"  learned_used={st.learned_used} balance {st.learned_balance:.2f} vs {st.sampling_balance:.2f}")
+        assert st.learned_used == 1
     ok, ov = _host(k, np.uint64), _host(v, np.uint64)
     del k, v
     torch.cuda.empty_cache()
@@ -128,6 +154,8 @@ def test_full_mixture_u64(mode):
     del src
     torch.cuda.empty_cache()
     say(f"  learned_used={st.learned_used}")
+    if mode == "learned":
+        assert st.learned_used == 1
     _check_keys(inp, out, 2)
 
 

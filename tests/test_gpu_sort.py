@@ -14,6 +14,7 @@ import workloads as W
 from oracle import dtsort_ref as R
 from oracle import sort as S
 from tests._dev import dev_u32, dev_u64, host_u32, host_u64, require_gpu, say
+from tests._seeds import seed_of
 
 pytestmark = pytest.mark.gpu
 
@@ -96,7 +97,9 @@ def _keys(kind, n, wide, rs):
 def test_distributions_u32(kind, params):
     require_gpu()
     say(f"u32 kind={kind} params={params}")
-    rs = np.random.default_rng(abs(hash((kind, str(params)))) % 2 ** 32)
+    sd = seed_of("u32", kind, str(params))
+    say(f"seed={sd}")
+    rs = np.random.default_rng(sd)
     k = _keys(kind, 400000, False, rs)
     got, st = _sort32(k, **params)
     assert np.array_equal(got, np.sort(k))
@@ -107,7 +110,9 @@ def test_distributions_u32(kind, params):
 def test_distributions_u64_and_pairs(kind, params):
     require_gpu()
     say(f"u64 kind={kind} params={params}")
-    rs = np.random.default_rng(abs(hash(("64", kind, str(params)))) % 2 ** 32)
+    sd = seed_of("64", kind, str(params))
+    say(f"seed={sd}")
+    rs = np.random.default_rng(sd)
     k = _keys(kind, 300000, True, rs)
     got, _ = _sort64(k, **params)
     assert np.array_equal(got, np.sort(k))
@@ -126,7 +131,9 @@ def test_nine_bit_digits(kind, wide):
     2048-counter variant.  Both against the definition."""
     require_gpu()
     say(f"nine-bit digits kind={kind} wide={wide}")
-    rs = np.random.default_rng(abs(hash(("nine", kind, wide))) % 2 ** 32)
+    sd = seed_of("nine", kind, wide)
+    say(f"seed={sd}")
+    rs = np.random.default_rng(sd)
     k = _keys(kind, 700001, wide, rs)
     sort = _sort64 if wide else _sort32
     for extra in (dict(), dict(ordered_ranks=1)):

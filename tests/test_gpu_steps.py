@@ -16,6 +16,7 @@ import torch
 from oracle import dtsort_ref as R
 from oracle import sort as S
 from tests._dev import dev_u32, dev_u64, host_u32, host_u64, require_gpu, say
+from tests._seeds import seed_of
 
 pytestmark = pytest.mark.gpu
 
@@ -80,7 +81,9 @@ def _gpu_plan(keys, hi, seed, g, plain, wide, skip=False):
 @pytest.mark.parametrize("kind,wide,g,plain", CASES)
 def test_step_plan(kind, wide, g, plain):
     require_gpu()
-    rs = np.random.default_rng(abs(hash((kind, wide, g))) % 2 ** 32)
+    sd = seed_of(kind, wide, g)
+    say(f"seed={sd}")
+    rs = np.random.default_rng(sd)
     n = 200000
     keys = _inputs(kind, n, rs, wide)
     hi = 64 if wide else 32
@@ -111,7 +114,9 @@ def test_step_plan_skip_and_lower_hi():
 def test_step_distribute(kind, wide, g, plain):
     require_gpu()
     lib = _lib()
-    rs = np.random.default_rng(abs(hash(("d", kind, wide, g))) % 2 ** 32)
+    sd = seed_of("d", kind, wide, g)
+    say(f"seed={sd}")
+    rs = np.random.default_rng(sd)
     n = 300001
     keys = _inputs(kind, n, rs, wide)
     hi = 64 if wide else 32

@@ -17,6 +17,7 @@ import pytest
 from oracle import dtsort_ref as R
 from oracle import rng
 from oracle import sort as S
+from tests._seeds import seed_of
 
 
 def test_splitmix64_published_sequence(golden_dir):
@@ -158,7 +159,7 @@ def _inputs(kind, n, rs):
 @pytest.mark.parametrize("cfg", [dict(), dict(gamma=3, cutoff=64), dict(gamma=5, cutoff=200, plain=True),
                                  dict(gamma=2, cutoff=8)])
 def test_recursive_method_equals_definition(kind, cfg):
-    rs = np.random.default_rng(hash((kind, str(cfg))) % 2 ** 32)
+    rs = np.random.default_rng(seed_of(kind, str(cfg)))
     n = 20000 if not cfg else 3000
     keys = _inputs(kind, n, rs)
     vals = np.arange(n, dtype=np.uint64)

@@ -219,6 +219,26 @@ int dtsort_mlp_forward(const float* params, const float* x, size_t n, float* pre
 int dtsort_mlp_train_u64(const uint64_t* sorted_keys, size_t n, uint64_t seed, int steps, int batch,
                          float lr, float* params, float* losses, void* stream);
 
+/* Allocation-free variant of dtsort_segmented, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments and result as
+ * dtsort_segmented; it runs the same kernels in the order of the graph form
+ * (opts->graph = 1: no host read-back, no synchronisation), enqueued directly
+ * on `stream`.  It calls no hipMalloc, hipFree or other allocating routine:
+ * every temporary buffer, and the ping-pong partner unless opts->workspace is
+ * given, lives in one static device array of 64 MiB that each device the
+ * library runs on holds until the process ends.  Inputs whose schedule needs
+ * more than that (about 2^22 keys without values, 2^21 with values, without a
+ * caller workspace) return DTSORT_EINVAL with a message naming the need.
+ * LEARNED mode, stats and profiling are rejected (DTSORT_EINVAL); invalid
+ * segment offsets are not reported (those segments are left as they are).
+ * All calls on one device share the array: calls whose work overlaps in time
+ * on one device (different streams, or host threads) race and must be
+ * serialised by the caller; a call made after the previous one's work was
+ * enqueued on the same stream is safe. */
+int dtsort_segmented_noalloc(uint32_t* keys, uint32_t* values, size_t n_total, const uint64_t* seg_offsets,
+                             size_t n_segments, const dtsort_opts* opts, void* stream);
+
 /* Plain copy of n 32-bit words from src to dst (device, not overlapping) with
  * the copy kernel the sorts use for finished buckets; enqueued on `stream`.
  * A measurement aid: the HBM rate this kernel reaches is the practical ceiling

@@ -12,7 +12,7 @@ import ctypes as C
 from . import _lib
 from ._lib import MODE_LEARNED, MODE_PLAIN, MODE_SAMPLING, DTSortError, Opts, Stats  # noqa: F401
 
-__all__ = ["sort_u32", "sort_u64", "sort_pairs_u64", "sort_segmented", "copy_u32", "make_opts", "Stats",
+__all__ = ["sort_u32", "sort_u64", "sort_pairs_u64", "sort_segmented", "sort_segmented_noalloc", "copy_u32", "make_opts", "Stats",
            "MODE_SAMPLING", "MODE_PLAIN", "MODE_LEARNED", "DTSortError"]
 
 
@@ -89,6 +89,23 @@ def sort_segmented(keys, offsets, values=None, opts: Opts | None = None):
     o = opts if opts is not None else make_opts()
     _lib.check(_lib.load().dtsort_segmented(keys.data_ptr(), vp, keys.numel(), offsets.data_ptr(),
                                             offsets.numel() - 1, C.byref(o), _stream(keys)))
+    return keys if values is None else (keys, values)
+
+
+def sort_segmented_noalloc(keys, offsets, values=None, opts: Opts | None = None):
+    """sort_segmented through the allocation-free entry point (buffers in the
+    library's static device scratch; inputs of up to about 2^22 keys)."""
+    _check_tensor(keys, 4)
+    _check_tensor(offsets, 8)
+    vp = None
+    if values is not None:
+        _check_tensor(values, 4)
+        if values.numel() != keys.numel():
+            raise ValueError("keys and values differ in length")
+        vp = values.data_ptr()
+    o = opts if opts is not None else make_opts()
+    _lib.check(_lib.load().dtsort_segmented_noalloc(keys.data_ptr(), vp, keys.numel(), offsets.data_ptr(),
+                                                    offsets.numel() - 1, C.byref(o), _stream(keys)))
     return keys if values is None else (keys, values)
 
 

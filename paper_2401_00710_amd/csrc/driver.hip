@@ -54,7 +54,7 @@ struct LevelKeep {
 struct Work {
   DevBuf tk;                      // ping-pong partner of keys (and values), unless the caller gives one
   DevBuf tasks[2], units, cm, leaf[LEAF_CLASSES + 1], copies, ctr;  // leaf[LEAF_PAIR]: paired halves
-  std::vector<LevelKeep> lv;
+  LevelKeep lv[MAX_LEVELS];  // kept per level until the merge phase
 };
 
 struct GraphEntry;
@@ -162,7 +162,6 @@ static int ensure(DevBuf& b, size_t bytes, hipStream_t s) {
 static Ctx* new_ctx(int dev) {
   Ctx* c = new Ctx();
   c->device = dev;
-  c->w.lv.resize(MAX_LEVELS);
   if (hipHostMalloc((void**)&c->h_ctr, sizeof(LevelCounters) * (MAX_LEVELS + 1)) != hipSuccess ||
       hipHostMalloc(&c->h_stage, 1 << 16) != hipSuccess ||
       hipEventCreateWithFlags(&c->done, hipEventDisableTiming) != hipSuccess) {
@@ -733,8 +732,7 @@ static GPlan graph_plan(const SortJob<K, V>& J, const Params& P) {
 }
 
 // Gives every buffer of the graph-form schedule its size through `place`
-// (an allocation, or a place in a caller's region); W.lv must already hold
-// g.levels entries.
+// (an allocation, or a place in a caller's region).
 template <typename Place>
 static int graph_buffers(Work& W, const GPlan& g, Place&& place) {
   int r;
@@ -760,7 +758,6 @@ static int graph_buffers(Work& W, const GPlan& g, Place&& place) {
 
 template <typename K, typename V>
 static int graph_alloc(Work& W, const GPlan& g, hipStream_t s) {
-  W.lv.resize(g.levels);
   return graph_buffers(W, g, [&](DevBuf& b, size_t bytes) { return ensure(b, bytes, s); });
 }
 
@@ -959,11 +956,14 @@ static int graph_sort(Ctx* c, SortJob<K, V>& J, void* user_ws, hipStream_t s, dt
   return 0;
 }
 
+// Checks the arguments of a sort call and fills J (all but the partner
+// buffer).  Returns DTSORT_OK or an error status (message set); *noop is set
+// when there is nothing to sort.
 template <typename K, typename V>
-static int sort_entry(K* keys, V* vals, size_t n, const uint64_t* seg, size_t n_seg, const dtsort_opts* opts,
-                      void* stream) {
+static int prepare_job(K* keys, V* vals, size_t n, const uint64_t* seg, size_t n_seg, const dtsort_opts* opts,
+                       SortJob<K, V>& J, bool* noop) {
   constexpr bool HV = HasVal<V>::value;
-  g_err.clear();
+  *noop = false;
   dtsort_opts o;
   dtsort_default_opts(&o);
   if (opts) o = *opts;
@@ -985,16 +985,11 @@ static int sort_entry(K* keys, V* vals, size_t n, const uint64_t* seg, size_t n_
   if (o.tile_shape < 0 || o.tile_shape > 6) return fail(DTSORT_EINVAL, "tile_shape out of range");
   if (o.graph && (o.mode == DTSORT_MODE_LEARNED || o.profile))
     return fail(DTSORT_EINVAL, "graph mode does not combine with LEARNED mode or profiling");
-  if (seg && n_seg == 0) return 0;
-  if (!seg && n <= 1) return 0;
   if (seg && n_seg >= (1ull << 31)) return fail(DTSORT_EINVAL, "too many segments");
-  hipStream_t s = (hipStream_t)stream;
-  Ctx* c;
-  int r;
-  if ((r = get_ctx(&c))) return r;
-  std::lock_guard<std::mutex> lk(g_mu);
-  if (c->has_last && c->last_stream != s) HIPCHK(hipStreamWaitEvent(s, c->done, 0));
-  SortJob<K, V> J;
+  if ((seg && n_seg == 0) || (!seg && n <= 1)) {
+    *noop = true;
+    return DTSORT_OK;
+  }
   J.n = n;
   J.seg = seg;
   J.n_seg = (uint32_t)n_seg;
@@ -1002,6 +997,32 @@ static int sort_entry(K* keys, V* vals, size_t n, const uint64_t* seg, size_t n_
   J.o = o;
   J.bufs.k[0] = keys;
   if constexpr (HV) J.bufs.v[0] = vals;
+  return DTSORT_OK;
+}
+
+// Points the partner halves of J's buffers into `ws` (keys, then values at
+// the next 256-byte boundary; dtsort_workspace_bytes covers both).
+template <typename K, typename V>
+static void set_partner(SortJob<K, V>& J, char* ws) {
+  J.bufs.k[1] = (K*)ws;
+  if constexpr (HasVal<V>::value) J.bufs.v[1] = (V*)(ws + ((J.n * sizeof(K) + 255) & ~(size_t)255));
+}
+
+template <typename K, typename V>
+static int sort_entry(K* keys, V* vals, size_t n, const uint64_t* seg, size_t n_seg, const dtsort_opts* opts,
+                      void* stream) {
+  constexpr bool HV = HasVal<V>::value;
+  g_err.clear();
+  SortJob<K, V> J;
+  bool noop = false;
+  int r;
+  if ((r = prepare_job(keys, vals, n, seg, n_seg, opts, J, &noop)) || noop) return r;
+  const dtsort_opts& o = J.o;
+  hipStream_t s = (hipStream_t)stream;
+  Ctx* c;
+  if ((r = get_ctx(&c))) return r;
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (c->has_last && c->last_stream != s) HIPCHK(hipStreamWaitEvent(s, c->done, 0));
   // ping-pong partner
   const size_t need = dtsort_workspace_bytes((int)sizeof(K), HV ? (int)sizeof(V) : 0, n);
   char* ws = nullptr;
@@ -1010,18 +1031,14 @@ static int sort_entry(K* keys, V* vals, size_t n, const uint64_t* seg, size_t n_
     ws = (char*)o.workspace;
   }
   if (o.graph) {
-    if (ws) {
-      J.bufs.k[1] = (K*)ws;
-      if constexpr (HV) J.bufs.v[1] = (V*)(ws + ((n * sizeof(K) + 255) & ~(size_t)255));
-    }
+    if (ws) set_partner(J, ws);
     r = graph_sort<K, V>(c, J, ws, s, o.stats);
   } else {
     if (!ws) {
       if ((r = ensure(c->w.tk, need, s))) return r;
       ws = (char*)c->w.tk.p;
     }
-    J.bufs.k[1] = (K*)ws;
-    if constexpr (HV) J.bufs.v[1] = (V*)(ws + ((n * sizeof(K) + 255) & ~(size_t)255));
+    set_partner(J, ws);
     r = run_sort<K, V>(c, J, s, o.stats);
   }
   if (hipEventRecord(c->done, s) == hipSuccess) {
@@ -1029,6 +1046,91 @@ static int sort_entry(K* keys, V* vals, size_t n, const uint64_t* seg, size_t n_
     c->last_stream = s;
   }
   return r;
+}
+
+// ------------------------------------------- allocation-free entry point
+// Device memory of dtsort_segmented_noalloc: every buffer of its schedule,
+// and the ping-pong partner unless the caller passes a workspace, is carved
+// from this one array.  Each device the library runs on holds its own copy
+// until the process ends.  In host code the array's name is not a device
+// address: the address is looked up once per device (hipGetSymbolAddress)
+// and only that address is handed to kernels.
+constexpr size_t NOALLOC_SCRATCH_BYTES = 64ull << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch[MAX_DEVICES];  // device address of `scratch`, per device
+
+static int scratch_of_current_device(char** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= MAX_DEVICES) return fail(DTSORT_EINVAL, "device index out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(DTSORT_EHIP, "hipGetSymbolAddress returned no address for the scratch array");
+    g_scratch[dev] = p;
+  }
+  *out = (char*)g_scratch[dev];
+  return 0;
+}
+
+// The graph-form schedule (kernels only, no host read-back) enqueued
+// directly on `stream`, with every buffer placed in the scratch array: no
+// device or pinned allocation, no synchronisation.
+template <typename K, typename V>
+static int noalloc_entry(K* keys, V* vals, size_t n, const uint64_t* seg, size_t n_seg, const dtsort_opts* opts,
+                         void* stream) {
+  constexpr bool HV = HasVal<V>::value;
+  g_err.clear();
+  SortJob<K, V> J;
+  bool noop = false;
+  int r;
+  if ((r = prepare_job(keys, vals, n, seg, n_seg, opts, J, &noop)) || noop) return r;
+  const dtsort_opts& o = J.o;
+  if (o.mode == DTSORT_MODE_LEARNED) return fail(DTSORT_EINVAL, "LEARNED mode is not available without allocation");
+  if (o.stats || o.profile) return fail(DTSORT_EINVAL, "stats and profiling read results back; not available here");
+  const Params P = resolve_params(J);
+  const GPlan g = graph_plan(J, P);
+  const size_t part = o.workspace ? 0 : dtsort_workspace_bytes((int)sizeof(K), HV ? (int)sizeof(V) : 0, n);
+  if (o.workspace && o.workspace_bytes < dtsort_workspace_bytes((int)sizeof(K), HV ? (int)sizeof(V) : 0, n))
+    return fail(DTSORT_EWORKSPACE, "workspace smaller than dtsort_workspace_bytes()");
+  // every buffer at a 256-byte boundary of the scratch array
+  auto rounded = [](size_t bytes) { return (std::max<size_t>(bytes, 64) + 255) & ~(size_t)255; };
+  Work W;
+  size_t need = part ? rounded(part) : 0;
+  (void)graph_buffers(W, g, [&](DevBuf&, size_t bytes) {
+    need += rounded(bytes);
+    return 0;
+  });
+  if (need > NOALLOC_SCRATCH_BYTES)
+    return fail(DTSORT_EINVAL, "input too large for the allocation-free entry point: it needs " +
+                                   std::to_string(need) + " bytes of scratch, the limit is " +
+                                   std::to_string(NOALLOC_SCRATCH_BYTES) +
+                                   (part ? " (a caller workspace for the partner buffer lowers the need)" : ""));
+  char* base = nullptr;
+  if ((r = scratch_of_current_device(&base))) return r;
+  size_t off = 0;
+  auto place = [&](DevBuf& b, size_t bytes) {
+    b.p = base + off;
+    b.cap = rounded(bytes);
+    off += b.cap;
+    return 0;
+  };
+  if (part) {
+    DevBuf pb;
+    place(pb, part);
+    set_partner(J, (char*)pb.p);
+  } else {
+    set_partner(J, (char*)o.workspace);
+  }
+  (void)graph_buffers(W, g, place);
+  hipStream_t s = (hipStream_t)stream;
+  graph_enqueue<K, V>(W, g, J, P, s);
+  HIPCHK(hipGetLastError());
+  return DTSORT_OK;
 }
 
 }  // namespace dts
@@ -1066,6 +1168,13 @@ int dtsort_segmented(uint32_t* keys, uint32_t* values, size_t n_total, const uin
   if (!seg_offsets && n_segments > 0) return fail(DTSORT_EINVAL, "seg_offsets is NULL");
   if (values) return sort_entry<uint32_t, uint32_t>(keys, values, n_total, seg_offsets, n_segments, opts, stream);
   return sort_entry<uint32_t, NoVal>(keys, (NoVal*)nullptr, n_total, seg_offsets, n_segments, opts, stream);
+}
+
+int dtsort_segmented_noalloc(uint32_t* keys, uint32_t* values, size_t n_total, const uint64_t* seg_offsets,
+                              size_t n_segments, const dtsort_opts* opts, void* stream) {
+  if (!seg_offsets && n_segments > 0) return fail(DTSORT_EINVAL, "seg_offsets is NULL");
+  if (values) return noalloc_entry<uint32_t, uint32_t>(keys, values, n_total, seg_offsets, n_segments, opts, stream);
+  return noalloc_entry<uint32_t, NoVal>(keys, (NoVal*)nullptr, n_total, seg_offsets, n_segments, opts, stream);
 }
 
 int dtsort_copy_u32(uint32_t* dst, const uint32_t* src, size_t n, void* stream) {

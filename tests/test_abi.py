@@ -137,3 +137,32 @@ def test_autotune_table_writer(tmp_path):
     autotune.write_table([(4, 0, 0, 0, 63, 9, 8192, 3)], str(p), "test")
     lines = [x for x in open(p) if not x.startswith("#")]
     assert lines == ["4 0 0 0 63 9 8192 3\n"]
+
+
+def test_noalloc_host_checks():
+    """The allocation-free entry point refuses, before any device work, what
+    its static scratch cannot hold and the options that need a read-back or
+    allocations."""
+    lib = L.load()
+    o = L.Opts()
+    lib.dtsort_default_opts(C.byref(o))
+    fake, seg = C.c_void_p(1 << 40), C.c_void_p(1 << 42)
+    assert lib.dtsort_segmented_noalloc(None, None, 0, None, 0, C.byref(o), None) == L.OK
+    assert lib.dtsort_segmented_noalloc(fake, None, 10, None, 3, C.byref(o), None) == L.EINVAL
+    assert lib.dtsort_segmented_noalloc(fake, None, 1 << 23, seg, 1, C.byref(o), None) == L.EINVAL
+    msg = lib.dtsort_last_error().decode()
+    assert "scratch" in msg and "67108864" in msg
+    assert lib.dtsort_segmented_noalloc(fake, C.c_void_p(1 << 41), 1 << 22, seg, 1, C.byref(o), None) == L.EINVAL
+    st = L.Stats()
+    o2 = L.Opts()
+    lib.dtsort_default_opts(C.byref(o2))
+    o2.stats = C.pointer(st)
+    assert lib.dtsort_segmented_noalloc(fake, None, 1000, seg, 1, C.byref(o2), None) == L.EINVAL
+    o3 = L.Opts()
+    lib.dtsort_default_opts(C.byref(o3))
+    o3.mode = L.MODE_LEARNED
+    assert lib.dtsort_segmented_noalloc(fake, None, 1000, seg, 1, C.byref(o3), None) == L.EINVAL
+    o4 = L.Opts()
+    lib.dtsort_default_opts(C.byref(o4))
+    o4.workspace, o4.workspace_bytes = C.c_void_p(1 << 43), 100
+    assert lib.dtsort_segmented_noalloc(fake, None, 1000, seg, 1, C.byref(o4), None) == L.EWORKSPACE

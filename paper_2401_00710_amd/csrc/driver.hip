@@ -311,10 +311,10 @@ static void fill_caps(LevelArgs& a, uint32_t n_tasks, uint64_t total, int gmax, 
   const uint64_t buckets = (uint64_t)n_tasks * nbc;
   a.caps.tasks = (uint32_t)std::min<uint64_t>(buckets, total / (cutoff + 1ull) + 1);
   a.caps.leaf = (uint32_t)std::min<uint64_t>(2 * buckets, total / 2 + 1);  // a paired bucket takes two entries
-  a.caps.copies = (uint32_t)std::min<uint64_t>(buckets + total / (1u << 20) + 1, total + 1);
+  a.caps.copies = (uint32_t)std::min<uint64_t>(buckets + total / COPY_PIECE + 1, total + 1);
   a.caps.merges = (uint32_t)std::min<uint64_t>((uint64_t)n_tasks << (gmax - 1), total + 1);
   a.caps.munits = (uint32_t)(total / 4096 + a.caps.merges + 1);
-  a.caps.spills = (uint32_t)(total / (1u << 20) + a.caps.merges + 1);
+  a.caps.spills = (uint32_t)(total / COPY_PIECE + a.caps.merges + 1);
 }
 
 static void add_stats(dtsort_stats* st, const LevelCounters& h, bool level) {
@@ -703,10 +703,10 @@ static GPlan graph_plan(const SortJob<K, V>& J, const Params& P) {
   Caps& c = g.caps;
   c.tasks = (uint32_t)tasks;
   c.leaf = (uint32_t)std::min<uint64_t>(2 * (tasks * nbc + J.n_seg + 1), n + 1);  // paired buckets: two entries
-  c.copies = (uint32_t)std::min<uint64_t>(tasks * nbc + n / (1u << 20) + 1, n + 1);
+  c.copies = (uint32_t)std::min<uint64_t>(tasks * nbc + n / COPY_PIECE + 1, n + 1);
   c.merges = (uint32_t)std::min<uint64_t>(tasks << (g.gmax - 1), n + 1);
   c.munits = (uint32_t)(n / 4096 + c.merges + 1);
-  c.spills = (uint32_t)(n / (1u << 20) + c.merges + 1);
+  c.spills = (uint32_t)(n / COPY_PIECE + c.merges + 1);
   c.units = (uint32_t)(n / 8192 + tasks + 1);
   c.cm = (uint64_t)c.units * nbc;
   const SlotLayout sl = slot_layout(g.gmax, false);
@@ -1163,6 +1163,10 @@ int dtsort_pairs_u64(uint64_t* keys, uint64_t* values, size_t n, const dtsort_op
   return sort_entry<uint64_t, uint64_t>(keys, values, n, nullptr, 0, opts, stream);
 }
 
+int dtsort_pairs_u32(uint32_t* keys, uint32_t* values, size_t n, const dtsort_opts* opts, void* stream) {
+  return sort_entry<uint32_t, uint32_t>(keys, values, n, nullptr, 0, opts, stream);
+}
+
 int dtsort_segmented(uint32_t* keys, uint32_t* values, size_t n_total, const uint64_t* seg_offsets, size_t n_segments,
                      const dtsort_opts* opts, void* stream) {
   if (!seg_offsets && n_segments > 0) return fail(DTSORT_EINVAL, "seg_offsets is NULL");
@@ -1189,30 +1193,16 @@ int dtsort_copy_u32(uint32_t* dst, const uint32_t* src, size_t n, void* stream) 
   int r;
   if ((r = get_ctx(&c))) return r;
   std::lock_guard<std::mutex> lk(g_mu);
-  // items of 2^20 words, as the sorts cut their copies
-  constexpr uint32_t PIECE = 1u << 20;
-  const uint32_t items = (uint32_t)(n / PIECE + (n % PIECE != 0 ? 1 : 0));
-  const size_t bytes = sizeof(Leaf) * items + 64;
-  if ((r = ensure(c->copy_items, bytes, s))) return r;
-  HIPCHK(hipStreamSynchronize(s));  // the pinned staging area is reused
-  if (bytes > (1u << 16)) return fail(DTSORT_EINVAL, "n too large for one call");
-  Leaf* hl = (Leaf*)c->h_stage;
-  for (uint32_t i = 0; i < items; ++i) {
-    hl[i].off = (uint64_t)i * PIECE;
-    hl[i].size = (uint32_t)std::min<uint64_t>(PIECE, n - (uint64_t)i * PIECE);
-    hl[i].bits = 0;
-    hl[i].from = 0;
-    hl[i].to = 1;
-    hl[i].pad = 0;
-  }
-  uint32_t* cnt = (uint32_t*)((char*)c->h_stage + sizeof(Leaf) * items);
-  *cnt = items;
-  HIPCHK(hipMemcpyAsync(c->copy_items.p, hl, sizeof(Leaf) * items + 4, hipMemcpyHostToDevice, s));
+  // items written on the device, cut as the sorts cut their copies
+  const uint32_t items = pieces_of((uint32_t)n);
+  if ((r = ensure(c->copy_items, sizeof(Leaf) * (size_t)items + 64, s))) return r;
+  Leaf* d_items = (Leaf*)c->copy_items.p;
+  uint32_t* d_count = (uint32_t*)((char*)c->copy_items.p + sizeof(Leaf) * (size_t)items);
+  launch_copy_items(d_items, d_count, n, s);
   Bufs<uint32_t, NoVal> b;
   b.k[0] = const_cast<uint32_t*>(src);
   b.k[1] = dst;
-  launch_copy<uint32_t, NoVal>((const Leaf*)c->copy_items.p,
-                               (const uint32_t*)((char*)c->copy_items.p + sizeof(Leaf) * items), items, items, b, s);
+  launch_copy<uint32_t, NoVal>(d_items, d_count, items, items, b, s);
   HIPCHK(hipGetLastError());
   return DTSORT_OK;
 }

@@ -17,9 +17,6 @@
 
 namespace dts {
 
-constexpr uint32_t COPY_PIECE = 1u << 20;   // records per copy item
-// Copy items of c records (no wrap-around for c near 2^32).
-__device__ __host__ inline uint32_t pieces_of(uint32_t c) { return c / COPY_PIECE + (c % COPY_PIECE != 0u ? 1u : 0u); }
 constexpr uint32_t MERGE_TILE = 4096;       // outputs per gather unit
 
 // Kinds of work a finished distribution hands on (one output list each).
@@ -276,6 +273,12 @@ __global__ __launch_bounds__(256) void k_children(LevelArgs a) {
   const uint64_t* SPL = (const uint64_t*)(slot + sl.spl);
   const int dst = 1 - t.src;
   const uint32_t zones = 1u << t.w;
+  const uint32_t ob = t.n_buckets - 1u;  // the overflow bucket
+  // A task whose digit took every remaining bit, with no heavy keys and an
+  // empty overflow bucket, leaves only finished buckets: when they lie in the
+  // wrong buffer, the whole task range is copied as one item list instead of
+  // bucket by bucket (the buckets are adjacent and in order).
+  const bool whole_copy = !learned && t.shift == 0 && t.n_heavy == 0 && st[ob + 1] == st[ob] && dst != t.tgt;
   Child ch[ZPT + 1];
   Merge mg[ZPT];
   uint32_t mslot[ZPT], uslot[ZPT], sslot[ZPT], spieces[ZPT];
@@ -284,7 +287,7 @@ __global__ __launch_bounds__(256) void k_children(LevelArgs a) {
     ch[k].kind = -1;
     mslot[k] = 0xFFFFFFFFu;
     const uint32_t z = threadIdx.x + 256u * k;
-    if (z >= zones) continue;
+    if (z >= zones || whole_copy) continue;
     const uint32_t lid = L[z];
     const uint32_t m = L[z + 1] - lid - 1u;
     const uint32_t s0 = st[lid];
@@ -333,10 +336,13 @@ __global__ __launch_bounds__(256) void k_children(LevelArgs a) {
   }
   ch[ZPT].kind = -1;
   if (threadIdx.x == 0) {
-    const uint32_t ob = t.n_buckets - 1u;
-    const uint32_t c = st[ob + 1] - st[ob];
-    if (c) atomicAdd(&r.st_over, (unsigned long long)c);
-    ch[ZPT] = plan_child(a, &r, t.off + st[ob], c, t.hi, dst, t.tgt, true);
+    if (whole_copy) {
+      ch[ZPT] = plan_child(a, &r, t.off, t.size, 0, dst, t.tgt, false);
+    } else {
+      const uint32_t c = st[ob + 1] - st[ob];
+      if (c) atomicAdd(&r.st_over, (unsigned long long)c);
+      ch[ZPT] = plan_child(a, &r, t.off + st[ob], c, t.hi, dst, t.tgt, true);
+    }
   }
   __syncthreads();
   reserve_global(a, &r);
@@ -390,19 +396,45 @@ void launch_children(const LevelArgs& a, Bufs<K, V> b, hipStream_t s) {
 }
 
 // ------------------------------------------------------------------ copies
+// d[0..n) = s[0..n).  When the two ranges share their alignment modulo 16
+// bytes (always for the sorts' own buffers, whose bases are 256-byte aligned),
+// the body moves in 16-byte words, four loads in flight per thread before the
+// stores; a head up to the first 16-byte boundary and the tail move record by
+// record.
+template <typename T>
+__device__ inline void copy_range(T* __restrict__ d, const T* __restrict__ s, uint32_t n) {
+  const uintptr_t sa = (uintptr_t)s, da = (uintptr_t)d;
+  if (((sa ^ da) & 15u) != 0u) {
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) d[i] = s[i];
+    return;
+  }
+  constexpr uint32_t PER = 16u / (uint32_t)sizeof(T);  // records per 16-byte word
+  const uint32_t head = min(n, (uint32_t)(((16u - (uint32_t)(sa & 15u)) & 15u) / (uint32_t)sizeof(T)));
+  const uint32_t nv = (n - head) / PER;
+  const uint32_t tail = head + nv * PER;
+  for (uint32_t i = threadIdx.x; i < head; i += blockDim.x) d[i] = s[i];
+  for (uint32_t i = tail + threadIdx.x; i < n; i += blockDim.x) d[i] = s[i];
+  const uint4* sv = reinterpret_cast<const uint4*>(s + head);
+  uint4* dv = reinterpret_cast<uint4*>(d + head);
+  const uint32_t B = blockDim.x;
+  uint32_t i = threadIdx.x;
+  for (; i + 3u * B < nv; i += 4u * B) {
+    const uint4 a = sv[i], b = sv[i + B], c = sv[i + 2u * B], e = sv[i + 3u * B];
+    dv[i] = a;
+    dv[i + B] = b;
+    dv[i + 2u * B] = c;
+    dv[i + 3u * B] = e;
+  }
+  for (; i < nv; i += B) dv[i] = sv[i];
+}
+
 template <typename K, typename V>
 __global__ __launch_bounds__(256) void k_copy(const Leaf* items, const uint32_t* count, uint32_t cap, Bufs<K, V> bf) {
   const uint32_t n_items = min(*count, cap);
   for (uint32_t ci = blockIdx.x; ci < n_items; ci += gridDim.x) {
     const Leaf it = items[ci];
-    const K* ki = bf.k[it.from] + it.off;
-    K* ko = bf.k[it.to] + it.off;
-    for (uint32_t i = threadIdx.x; i < it.size; i += 256) ko[i] = ki[i];
-    if constexpr (HasVal<V>::value) {
-      const V* vi = bf.v[it.from] + it.off;
-      V* vo = bf.v[it.to] + it.off;
-      for (uint32_t i = threadIdx.x; i < it.size; i += 256) vo[i] = vi[i];
-    }
+    copy_range<K>(bf.k[it.to] + it.off, bf.k[it.from] + it.off, it.size);
+    if constexpr (HasVal<V>::value) copy_range<V>(bf.v[it.to] + it.off, bf.v[it.from] + it.off, it.size);
   }
 }
 
@@ -410,6 +442,28 @@ template <typename K, typename V>
 void launch_copy(const Leaf* items, const uint32_t* count, uint32_t cap, uint32_t grid, Bufs<K, V> b, hipStream_t s) {
   if (grid == 0 || cap == 0) return;
   hipLaunchKernelGGL((k_copy<K, V>), dim3(grid), dim3(256), 0, s, items, count, cap, b);
+}
+
+// Copy items of a plain copy of n records from buffer 0 to buffer 1, cut
+// like the sorts' copies (pieces of COPY_PIECE records); count = items.
+__global__ __launch_bounds__(256) void k_copy_items(Leaf* items, uint32_t* count, uint64_t n) {
+  const uint32_t n_items = pieces_of((uint32_t)n);
+  for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < n_items; i += gridDim.x * 256) {
+    Leaf l;
+    l.off = (uint64_t)i * COPY_PIECE;
+    l.size = (uint32_t)min((uint64_t)COPY_PIECE, n - l.off);
+    l.bits = 0;
+    l.from = 0;
+    l.to = 1;
+    l.pad = 0;
+    items[i] = l;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) *count = n_items;
+}
+
+void launch_copy_items(Leaf* items, uint32_t* count, uint64_t n, hipStream_t s) {
+  const uint32_t n_items = pieces_of((uint32_t)n);
+  hipLaunchKernelGGL(k_copy_items, dim3(n_items / 256 + 1), dim3(256), 0, s, items, count, n);
 }
 
 // ------------------------------------------------------------------ merges

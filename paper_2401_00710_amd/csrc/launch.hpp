@@ -100,6 +100,15 @@ template <typename K, typename V>
 void launch_finish(const Task* tasks, const uint32_t* count, uint32_t cap, uint32_t grid, Bufs<K, V> b,
                    hipStream_t s);
 
+// Copies move pieces of at most COPY_PIECE records (one workgroup a piece):
+// a large finished bucket becomes several items.
+constexpr uint32_t COPY_PIECE = 1u << 16;
+__device__ __host__ inline uint32_t pieces_of(uint32_t c) { return c / COPY_PIECE + (c % COPY_PIECE != 0u ? 1u : 0u); }
+
+// Items (and their count) of a plain copy of n < 2^32 records from buffer 0
+// to buffer 1; `items` holds pieces_of(n).
+void launch_copy_items(Leaf* items, uint32_t* count, uint64_t n, hipStream_t s);
+
 template <typename K, typename V>
 void launch_copy(const Leaf* items, const uint32_t* count, uint32_t cap, uint32_t grid, Bufs<K, V> b, hipStream_t s);
 

@@ -148,12 +148,17 @@ def main():
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1 << 27, help="keys per input for the multicore baseline")
     ap.add_argument("--cpu-sample-1core", type=int, default=1 << 24, help="keys per input for the one-core baseline")
+    ap.add_argument("--grid", action="store_true",
+                    help="the paper's synthetic grid (Tab. synthetic) as 32+32 and 64+64 records, heavy-key "
+                         "detection on (sampling) and off (plain); prints one JSON line")
     ap.add_argument("--once", default=None, metavar="WORKLOAD",
                     help="for profilers: generate WORKLOAD, sort it once (tuned), print its time and exit; one of "
                          + ", ".join(ONCE))
     args = ap.parse_args()
     if args.once:
         return run_once(args.once, int(args.n))
+    if args.grid:
+        return run_grid(args)
     if args.gpus != 1:
         print(json.dumps({"error": "the benchmark runs on one GPU; --gpus above 1 is not supported "
                                    "(the sort has no multi-GPU path)"}), flush=True)
@@ -355,6 +360,87 @@ def run_once(name, n):
         torch.cuda.synchronize()
         times.append(e0.elapsed_time(e1))
     print(json.dumps({"once": name, "ms": round(times[-1], 4)}), flush=True)
+
+
+# The paper's times on its 96-core machine (Tab. synthetic, seconds for 10^9
+# records), quoted as context: family -> (32+32 times, 64+64 times) in the
+# parameter order of workloads.PAPER_GRID.
+PAPER_GRID_S = {
+    "unif": ((0.308, 0.506, 0.478, 0.501, 0.500), (0.581, 0.795, 0.859, 1.03, 0.994)),
+    "exp": ((0.526, 0.502, 0.435, 0.419, 0.402), (0.976, 0.919, 0.819, 0.782, 0.763)),
+    "zipf": ((0.493, 0.524, 0.601, 0.516, 0.446), (1.00, 1.00, 1.04, 0.918, 0.883)),
+    "bexp": ((1.11, 0.643, 0.550, 0.512, 0.616), (3.30, 2.75, 1.85, 1.42, 1.32)),
+}
+
+
+def run_grid(args):
+    """Every instance of the paper's synthetic grid at n records (default
+    10^9) as (32-bit key, 32-bit value) and (64-bit key, 64-bit value)
+    records with value = index: one warm-up and `steps` timed sorts each
+    (median), tuned parameters, with heavy-key detection (sampling) and
+    without it (plain, the paper's ablation)."""
+    import numpy as np
+    import torch
+
+    import paper_2401_00710_amd as dt
+    import workloads as W
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    n = int(args.n)
+    steps = max(1, min(args.steps, 5))
+    res = {}
+    for bits in (32, 64):
+        vt = torch.int32 if bits == 32 else torch.int64
+        srt = dt.sort_pairs_u32 if bits == 32 else dt.sort_pairs_u64
+        k = v = kw = vw = None
+        for fam, params in W.PAPER_GRID.items():
+            for i, prm in enumerate(params):
+                name = f"{fam}-{prm:g}/{bits}"
+                log(f"grid {name}")
+                del k, v, kw, vw
+                torch.cuda.empty_cache()
+                k = W.paper_keys(fam, prm, n, bits, seed=0, device=dev)
+                k = k.to(torch.int32) if bits == 32 else k
+                v = torch.arange(n, dtype=vt, device=dev)
+                kw, vw = torch.empty_like(k), torch.empty_like(v)
+                row = {}
+                for mode, mname in ((dt.MODE_SAMPLING, "sampling"), (dt.MODE_PLAIN, "plain")):
+                    st = dt.Stats()
+                    o = dt.make_opts(tuned=1, mode=mode, stats=st)
+                    ts = timed_sorts(lambda: srt(kw, vw, o), k, kw, steps, 1, v, vw)
+                    m = statistics.median(ts)
+                    row[mname] = {"ms": round(m, 3), "Grec_s": round(n / (m / 1e3) / 1e9, 3),
+                                  "levels": int(st.levels), "heavy_keys": int(st.heavy_keys),
+                                  "merged_records": int(st.records_merged)}
+                w64 = kw.to(torch.int64) & (0xFFFFFFFF if bits == 32 else -1)
+                if bits == 32:
+                    ok = bool((w64[1:] >= w64[:-1]).all().item())
+                else:  # unsigned order of int64 bit patterns
+                    ws = w64 ^ (-(2 ** 63))
+                    ok = bool((ws[1:] >= ws[:-1]).all().item())
+                row["sorted_ok"] = ok
+                row["plain_over_sampling"] = round(row["plain"]["ms"] / row["sampling"]["ms"], 3)
+                ps = PAPER_GRID_S[fam][0 if bits == 32 else 1][i]
+                row["paper_96core_s"] = ps
+                row["vs_paper_96core"] = round(ps * 1e3 / row["sampling"]["ms"], 2)
+                res[name] = row
+        del k, v, kw, vw
+        torch.cuda.empty_cache()
+
+    def gm(xs):
+        return round(math.exp(sum(math.log(x) for x in xs) / len(xs)), 3)
+    summary = {}
+    for bits in (32, 64):
+        for grp, fams in (("standard", ("unif", "exp", "zipf")), ("bexp", ("bexp",))):
+            rows = [r for kname, r in res.items() if kname.endswith(f"/{bits}") and kname.split("-")[0] in fams]
+            summary[f"{grp}/{bits}"] = {
+                "geomean_ms_sampling": gm([r["sampling"]["ms"] for r in rows]),
+                "geomean_ms_plain": gm([r["plain"]["ms"] for r in rows]),
+                "geomean_plain_over_sampling": gm([r["plain_over_sampling"] for r in rows]),
+                "geomean_paper_96core_s": gm([r["paper_96core_s"] for r in rows])}
+    print(json.dumps({"grid": "paper synthetic distributions (Tab. synthetic), records with value = index",
+                      "n": n, "steps": steps, "timing": "median of steps after one warm-up, HIP events",
+                      "summary": summary, "instances": res}), flush=True)
 
 
 def run_extra(dt, W, torch, np, n, args, opts):

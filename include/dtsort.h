@@ -146,6 +146,12 @@ int dtsort_u64(uint64_t* keys, size_t n, const dtsort_opts* opts, void* stream);
  * not overlap. */
 int dtsort_pairs_u64(uint64_t* keys, uint64_t* values, size_t n, const dtsort_opts* opts, void* stream);
 
+/* Stable sort of n (32-bit key, 32-bit value) records stored as two arrays,
+ * the record layout of the paper's 32-bit experiments (Section 6: 32-bit
+ * keys with 32-bit values); values move with their keys.  keys and values
+ * must not overlap. */
+int dtsort_pairs_u32(uint32_t* keys, uint32_t* values, size_t n, const dtsort_opts* opts, void* stream);
+
 /* Batched form: n_segments independent stable sorts of 32-bit keys (and
  * optional 32-bit values, NULL for keys only) stored back to back.  Segment s
  * is [seg_offsets[s], seg_offsets[s+1]); seg_offsets is a DEVICE array of

@@ -12,7 +12,7 @@ import ctypes as C
 from . import _lib
 from ._lib import MODE_LEARNED, MODE_PLAIN, MODE_SAMPLING, DTSortError, Opts, Stats  # noqa: F401
 
-__all__ = ["sort_u32", "sort_u64", "sort_pairs_u64", "sort_segmented", "sort_segmented_noalloc", "copy_u32", "make_opts", "Stats",
+__all__ = ["sort_u32", "sort_u64", "sort_pairs_u64", "sort_pairs_u32", "sort_segmented", "sort_segmented_noalloc", "copy_u32", "make_opts", "Stats",
            "MODE_SAMPLING", "MODE_PLAIN", "MODE_LEARNED", "DTSortError"]
 
 
@@ -71,6 +71,18 @@ def sort_pairs_u64(keys, values, opts: Opts | None = None):
         raise ValueError("keys and values differ in length")
     o = opts if opts is not None else make_opts()
     _lib.check(_lib.load().dtsort_pairs_u64(keys.data_ptr(), values.data_ptr(), keys.numel(), C.byref(o),
+                                            _stream(keys)))
+    return keys, values
+
+
+def sort_pairs_u32(keys, values, opts: Opts | None = None):
+    """Stable in-place sort of (32-bit key, 32-bit value) records by key."""
+    _check_tensor(keys, 4)
+    _check_tensor(values, 4)
+    if values.numel() != keys.numel():
+        raise ValueError("keys and values differ in length")
+    o = opts if opts is not None else make_opts()
+    _lib.check(_lib.load().dtsort_pairs_u32(keys.data_ptr(), values.data_ptr(), keys.numel(), C.byref(o),
                                             _stream(keys)))
     return keys, values
 

@@ -79,6 +79,7 @@ _SIGS = {
     "dtsort_u32": (_I, [_P, _Z, C.POINTER(Opts), _P]),
     "dtsort_u64": (_I, [_P, _Z, C.POINTER(Opts), _P]),
     "dtsort_pairs_u64": (_I, [_P, _P, _Z, C.POINTER(Opts), _P]),
+    "dtsort_pairs_u32": (_I, [_P, _P, _Z, C.POINTER(Opts), _P]),
     "dtsort_segmented": (_I, [_P, _P, _Z, _P, _Z, C.POINTER(Opts), _P]),
     "dtsort_segmented_noalloc": (_I, [_P, _P, _Z, _P, _Z, C.POINTER(Opts), _P]),
     "dtsort_step_plan_u32": (_I, [_P, _Z, _I, _I, C.POINTER(Opts), _P, _P, _P, _P]),

@@ -75,3 +75,68 @@ def test_make_config_small():
         if name == "segmented_u32":
             off = c["offsets"]
             assert int(off[0]) == 0 and int(off[-1]) == c["keys"].numel()
+
+
+def test_paper_grid_unif_distinct_keys():
+    """Unif-mu: at most mu distinct keys, all of them hit when n >> mu, spread
+    over the whole key range by the bijection."""
+    for bits in (32, 64):
+        k = W.paper_keys("unif", 1000, 1 << 17, bits, seed=1).numpy().view(np.uint64)
+        u = np.unique(k)
+        assert u.size == 1000
+        assert int(u.max()) > 2 ** (bits - 2)
+        k7 = W.paper_keys("unif", 10, 4096, bits, seed=2)
+        assert torch.unique(k7).numel() == 10
+
+
+def test_paper_grid_exp_frequencies():
+    """Exp-lambda: rounded exponential of rate 1e-5 lambda; the frequency of
+    the rounded value 0 is P(X < 0.5) = 1 - exp(-0.5 rate); keys bijected."""
+    n = 1 << 18
+    for lam in (1, 10):
+        rate = 1e-5 * lam
+        k = W.paper_keys("exp", lam, n, 64, seed=3)
+        inv = W.feistel64(torch.zeros(1, dtype=torch.int64), 3 * 131 + 17)  # the key of value 0
+        p0 = 1 - math.exp(-0.5 * rate)
+        share = float((k == inv[0]).double().mean())
+        assert abs(share - p0) < 5 * math.sqrt(p0 / n) + 1e-6
+    # the number of distinct keys is about the range of rounded values actually drawn
+    k = W.paper_keys("exp", 10, n, 32, seed=4)
+    assert 4000 < torch.unique(k).numel() < 60000
+
+
+def test_paper_grid_zipf_head():
+    n = 1 << 17
+    k = W.paper_keys("zipf", 1.5, n, 32, seed=5)
+    top = torch.unique(k, return_counts=True)[1].max().item() / n
+    Z = sum(i ** -1.5 for i in range(1, 200000)) + 2 / math.sqrt(200000)
+    assert abs(top - 1 / Z) < 5 * math.sqrt(1 / Z / n)
+
+
+def test_paper_grid_bexp_bits():
+    """BExp-t: every bit is 0 with probability 1/t, independently."""
+    n = 1 << 16
+    for bits, t in ((32, 10), (64, 300)):
+        k = W.paper_keys("bexp", t, n, bits, seed=6).numpy().view(np.uint64)
+        for b in (0, 1, bits // 2, bits - 1):
+            zeros = np.mean(((k >> np.uint64(b)) & np.uint64(1)) == 0)
+            assert abs(zeros - 1 / t) < 5 * math.sqrt((1 / t) / n), (bits, t, b)
+        if bits == 32:
+            assert int(k.max()) < 2 ** 32
+    # all ones is the most frequent 32-bit key: P = (1 - 1/t)^32
+    k = W.paper_keys("bexp", 10, n, 32, seed=7).numpy().view(np.uint64)
+    p = 0.9 ** 32
+    assert abs(np.mean(k == 2 ** 32 - 1) - p) < 5 * math.sqrt(p / n)
+
+
+def test_paper_grid_chunks_deterministic(monkeypatch):
+    """Generated in chunks: the result does not depend on the chunk size, and
+    a prefix equals the same call at a smaller n."""
+    from workloads import gen
+    for fam, prm in (("unif", 10 ** 5), ("exp", 2), ("bexp", 30)):
+        a = W.paper_keys(fam, prm, 5000, 64, seed=8)
+        b = W.paper_keys(fam, prm, 3000, 64, seed=8)
+        assert torch.equal(a[:3000], b)
+        monkeypatch.setattr(gen, "_CHUNK", 777)
+        assert torch.equal(W.paper_keys(fam, prm, 5000, 64, seed=8), a)
+        monkeypatch.undo()

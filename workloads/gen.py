@@ -235,6 +235,77 @@ def segmented_u32(sizes: torch.Tensor, seed: int = 0, device="cpu"):
     return keys, offsets
 
 
+# ------------------------------------------- the paper's synthetic grid
+# Section 6 (Tab. synthetic): Unif-mu (mu distinct keys), Exp-lambda
+# (exponential with rate 1e-5 * lambda, rounded to the closest integer),
+# Zipf-s (ranks 1..n with P(k) ~ k^-s) and BExp-t (every bit of a key is 0
+# with probability 1/t, else 1).  The three standard families are mapped to
+# the full key range by a seeded bijection of the key width (the paper maps
+# them "to larger ranges ... to test the full range"); BExp keys are used as
+# drawn.  Width 32 or 64; int64 bit patterns.
+PAPER_GRID = {
+    "unif": (10, 10 ** 3, 10 ** 5, 10 ** 7, 10 ** 9),
+    "exp": (1, 2, 5, 7, 10),
+    "zipf": (0.6, 0.8, 1.0, 1.2, 1.5),
+    "bexp": (10, 30, 50, 100, 300),
+}
+
+_CHUNK = 1 << 26  # keys generated per pass (bounds temporary memory)
+
+
+def _biject(x: torch.Tensor, bits: int, key: int) -> torch.Tensor:
+    return feistel32(x, key) if bits == 32 else feistel64(x, key)
+
+
+def paper_bexp(n: int, t: float, bits: int, seed: int = 0, device="cpu", stream: int = 40) -> torch.Tensor:
+    """BExp-t: every bit independently 0 with probability 1/t.  A bit is 0
+    when its own 32-bit uniform is below floor(2^32 / t) (two bits per 64-bit
+    word of the generator)."""
+    thr = int((1 << 32) // t)
+    out = torch.empty(n, dtype=torch.int64, device=device)
+    for c0 in range(0, n, _CHUNK):
+        m = min(_CHUNK, n - c0)
+        k = torch.zeros(m, dtype=torch.int64, device=device)
+        for j in range(bits // 2):
+            w = rand64(seed, stream * 64 + j, m, device, start=c0)
+            lo = (w & 0xFFFFFFFF) >= thr
+            hi = _lsr(w, 32) >= thr
+            k |= (lo.to(torch.int64) << (2 * j)) | (hi.to(torch.int64) << (2 * j + 1))
+        out[c0:c0 + m] = k
+    return out
+
+
+def paper_keys(family: str, param: float, n: int, bits: int, seed: int = 0, device="cpu") -> torch.Tensor:
+    """n keys of one instance of the paper's synthetic grid (see PAPER_GRID)."""
+    if bits not in (32, 64):
+        raise ValueError("bits must be 32 or 64")
+    key = seed * 131 + 17
+    if family == "unif":
+        mu = int(param)
+        out = torch.empty(n, dtype=torch.int64, device=device)
+        for c0 in range(0, n, _CHUNK):
+            m = min(_CHUNK, n - c0)
+            u = uniform01(seed, 30, m, device, start=c0)
+            r = torch.clamp(torch.floor(u * mu).to(torch.int64), max=mu - 1)
+            out[c0:c0 + m] = _biject(r, bits, key)
+        return out
+    if family == "exp":
+        rate = 1e-5 * float(param)
+        out = torch.empty(n, dtype=torch.int64, device=device)
+        for c0 in range(0, n, _CHUNK):
+            m = min(_CHUNK, n - c0)
+            u = uniform01(seed, 31, m, device, start=c0)
+            x = torch.round(-torch.log1p(-u) / rate).to(torch.int64)
+            out[c0:c0 + m] = _biject(x, bits, key)
+        return out
+    if family == "zipf":
+        r = zipf_ranks(n, float(param), n, seed, device, stream=32)
+        return _biject(r, bits, key)
+    if family == "bexp":
+        return paper_bexp(n, float(param), bits, seed, device)
+    raise KeyError(family)
+
+
 # ---------------------------------------------------------------- configs
 CONFIGS = {
     # name: (key dtype, has values, default n)

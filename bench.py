@@ -151,6 +151,9 @@ def main():
     ap.add_argument("--grid", action="store_true",
                     help="the paper's synthetic grid (Tab. synthetic) as 32+32 and 64+64 records, heavy-key "
                          "detection on (sampling) and off (plain); prints one JSON line")
+    ap.add_argument("--merge-study", action="store_true",
+                    help="the paper's merge study (Section 6.3): seven distributions, 32+32 and 64+64 records, "
+                         "the dovetail merge as a gather, PLMerge-style, Alg. 3 in place, and no merge")
     ap.add_argument("--once", default=None, metavar="WORKLOAD",
                     help="for profilers: generate WORKLOAD, sort it once (tuned), print its time and exit; one of "
                          + ", ".join(ONCE))
@@ -159,6 +162,8 @@ def main():
         return run_once(args.once, int(args.n))
     if args.grid:
         return run_grid(args)
+    if args.merge_study:
+        return run_merge_study(args)
     if args.gpus != 1:
         print(json.dumps({"error": "the benchmark runs on one GPU; --gpus above 1 is not supported "
                                    "(the sort has no multi-GPU path)"}), flush=True)
@@ -441,6 +446,62 @@ def run_grid(args):
     print(json.dumps({"grid": "paper synthetic distributions (Tab. synthetic), records with value = index",
                       "n": n, "steps": steps, "timing": "median of steps after one warm-up, HIP events",
                       "summary": summary, "instances": res}), flush=True)
+
+
+MERGE_STUDY = (("unif", 1000), ("exp", 1), ("exp", 10), ("zipf", 0.6), ("zipf", 1.5), ("bexp", 10), ("bexp", 300))
+
+
+def run_merge_study(args):
+    """The paper's merge study (Section 6.3, Fig. scale c-d): for its seven
+    distributions (Unif-10^3, and the lightest and heaviest of Exp, Zipf and
+    BExp), sorts of n records with each Step 4 implementation and with none
+    (the time of the other steps); the merge share is (t - t_none) / t."""
+    import torch
+
+    import paper_2401_00710_amd as dt
+    import workloads as W
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    n = int(args.n)
+    steps = max(1, min(args.steps, 5))
+    variants = (("dtmerge_gather", dt.MERGE_GATHER), ("plmerge", dt.MERGE_PLMERGE),
+                ("dtmerge_inplace", dt.MERGE_INPLACE), ("no_merge", dt.MERGE_NONE))
+    res = {}
+    for bits in (32, 64):
+        vt = torch.int32 if bits == 32 else torch.int64
+        srt = dt.sort_pairs_u32 if bits == 32 else dt.sort_pairs_u64
+        k = v = kw = vw = None
+        for fam, prm in MERGE_STUDY:
+            name = f"{fam}-{prm:g}/{bits}"
+            log(f"merge study {name}")
+            del k, v, kw, vw
+            torch.cuda.empty_cache()
+            k = W.paper_keys(fam, prm, n, bits, seed=0, device=dev)
+            k = k.to(torch.int32) if bits == 32 else k
+            v = torch.arange(n, dtype=vt, device=dev)
+            kw, vw = torch.empty_like(k), torch.empty_like(v)
+            row = {}
+            for vname, mv in variants:
+                st = dt.Stats()
+                o = dt.make_opts(tuned=1, merge_variant=mv, stats=st)
+                ts = timed_sorts(lambda: srt(kw, vw, o), k, kw, steps, 1, v, vw)
+                row[vname] = {"ms": round(statistics.median(ts), 3)}
+                if mv == dt.MERGE_GATHER:
+                    row["merged_records"] = int(st.records_merged)
+                    row["merges"] = int(st.merges)
+            t0 = row["no_merge"]["ms"]
+            for vname, _ in variants[:3]:
+                t = row[vname]["ms"]
+                row[vname]["merge_ms"] = round(t - t0, 3)
+                row[vname]["merge_share"] = round((t - t0) / t, 3)
+            row["plmerge_over_gather"] = round(row["plmerge"]["ms"] / row["dtmerge_gather"]["ms"], 3)
+            row["inplace_over_gather"] = round(row["dtmerge_inplace"]["ms"] / row["dtmerge_gather"]["ms"], 3)
+            res[name] = row
+        del k, v, kw, vw
+        torch.cuda.empty_cache()
+    print(json.dumps({"merge_study": "Section 6.3 merge study, records with value = index", "n": n,
+                      "steps": steps, "timing": "median of steps after one warm-up, HIP events",
+                      "instances": res}), flush=True)
 
 
 def run_extra(dt, W, torch, np, n, args, opts):

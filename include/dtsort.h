@@ -122,6 +122,16 @@ typedef struct dtsort_opts {
                              shape (levels, tasks, heavy keys) depends on the seed alone (Appendix A);
                              0 (default) = unordered ranks from LDS atomics, faster.  Equal keys cannot
                              be told apart, so the sorted output is the same either way. */
+  int32_t merge_variant;  /* Step 4 (Section 3.4) implementation, for the paper's merge study (Section 6.3):
+                             0 = the dovetail merge as one out-of-place gather (default);
+                             1 = PLMerge-style: a general parallel merge (merge path) of the zone's light
+                                 run with its heavy runs into the partner buffer, then copied back;
+                             2 = Alg. 3 literally: the zone gathered in one buffer, the smaller side copied
+                                 out, heavy buckets moved one by one (two flips where a bucket overlaps its
+                                 destination), the copied side moved back;
+                             3 = no merge: zones with heavy keys are left unmerged, so the output is NOT
+                                 sorted (a timing knob for the other steps).
+                             Variants 0-2 give the same sorted output. */
   void* workspace;        /* optional device buffer for the ping-pong partner (see dtsort_workspace_bytes) */
   size_t workspace_bytes;
   dtsort_stats* stats;    /* optional host pointer */

@@ -13,6 +13,7 @@ LIB_PATH = os.path.join(_HERE, "libdtsort.so")
 
 OK, EINVAL, ENOMEM, EWORKSPACE, EHIP, EINTERNAL = 0, -1, -2, -3, -4, -5
 MODE_SAMPLING, MODE_PLAIN, MODE_LEARNED = 0, 1, 2
+MERGE_GATHER, MERGE_PLMERGE, MERGE_INPLACE, MERGE_NONE = 0, 1, 2, 3
 
 
 class Stats(C.Structure):
@@ -64,6 +65,7 @@ class Opts(C.Structure):
         ("tile_shape", C.c_int32),
         ("graph", C.c_int32),
         ("ordered_ranks", C.c_int32),
+        ("merge_variant", C.c_int32),
         ("workspace", C.c_void_p),
         ("workspace_bytes", C.c_size_t),
         ("stats", C.POINTER(Stats)),

@@ -447,6 +447,7 @@ static int run_sort(Ctx* c, SortJob<K, V>& J, hipStream_t s, dtsort_stats* stats
   a.key_bits = J.key_bits;
   a.tile = P.tile;
   a.ordered = o.ordered_ranks != 0;
+  a.merge_variant = o.merge_variant;
   if (stats) std::memset(stats, 0, sizeof(*stats));
 
   int r;
@@ -649,14 +650,14 @@ static int run_sort(Ctx* c, SortJob<K, V>& J, hipStream_t s, dtsort_stats* stats
     cur = 1 - cur;
   }
   // ---- dovetail merges, deepest level first
-  for (int l = L - 1; l >= 0; --l) {
+  for (int l = L - 1; l >= 0 && o.merge_variant != MV_NONE; --l) {
     LevelKeep& K_ = W.lv[l];
     if (K_.n_merges == 0) continue;
     LevelCounters* lc = dctr + l + 1;
     prof.begin(PK_MERGE);
     launch_copy<K, V>((Leaf*)K_.spills.p, &lc->spills, K_.caps.spills, K_.n_spills, J.bufs, s);
     launch_merge<K, V>((Merge*)K_.merges.p, &lc->merges, K_.caps.merges, K_.n_merges, (uint2*)K_.munits.p,
-                       &lc->merge_units, K_.caps.munits, K_.n_munits, (uint8_t*)K_.tab.p, J.bufs, s);
+                       &lc->merge_units, K_.caps.munits, K_.n_munits, (uint8_t*)K_.tab.p, J.bufs, o.merge_variant, s);
     prof.end(2.0 * rec_bytes * K_.merge_records);
     HIPCHK(hipGetLastError());
   }
@@ -775,6 +776,7 @@ static void graph_enqueue(Work& W, const GPlan& g, const SortJob<K, V>& J, const
   a.key_bits = J.key_bits;
   a.tile = P.tile;
   a.ordered = J.o.ordered_ranks != 0;
+  a.merge_variant = J.o.merge_variant;
   a.caps = g.caps;
   LevelCounters* dctr = (LevelCounters*)W.ctr.p;
   for (int k = 0; k <= LEAF_PAIR; ++k) a.leaf[k] = (Leaf*)W.leaf[k].p;
@@ -822,12 +824,13 @@ static void graph_enqueue(Work& W, const GPlan& g, const SortJob<K, V>& J, const
   // tasks created by the last recorded level
   launch_finish<K, V>((const Task*)W.tasks[g.levels & 1].p, &dctr[g.levels].next_tasks, g.caps.tasks, g.grid_finish,
                       J.bufs, s);
-  for (int L = g.levels - 1; L >= 0; --L) {
+  for (int L = g.levels - 1; L >= 0 && J.o.merge_variant != MV_NONE; --L) {
     LevelKeep& K_ = W.lv[L];
     LevelCounters* lc = dctr + L + 1;
     launch_copy<K, V>((Leaf*)K_.spills.p, &lc->spills, g.caps.spills, g.grid_spill, J.bufs, s);
     launch_merge<K, V>((Merge*)K_.merges.p, &lc->merges, g.caps.merges, g.grid_mpos, (uint2*)K_.munits.p,
-                       &lc->merge_units, g.caps.munits, g.grid_munit, (uint8_t*)K_.tab.p, J.bufs, s);
+                       &lc->merge_units, g.caps.munits, g.grid_munit, (uint8_t*)K_.tab.p, J.bufs, J.o.merge_variant,
+                       s);
   }
 }
 
@@ -838,12 +841,13 @@ struct GraphKey {
   const uint64_t* seg;
   uint32_t n_seg;
   uint64_t seed;
-  int key_bits, mode, gover, tile, levels, ordered;
+  int key_bits, mode, gover, tile, levels, ordered, merge_variant;
   uint32_t cutoff;
   bool operator==(const GraphKey& o) const {
     return kb == o.kb && vb == o.vb && k == o.k && v == o.v && ws == o.ws && n == o.n && seg == o.seg &&
            n_seg == o.n_seg && seed == o.seed && key_bits == o.key_bits && mode == o.mode && gover == o.gover &&
-           tile == o.tile && levels == o.levels && cutoff == o.cutoff && ordered == o.ordered;
+           tile == o.tile && levels == o.levels && cutoff == o.cutoff && ordered == o.ordered &&
+           merge_variant == o.merge_variant;
   }
 };
 
@@ -886,6 +890,7 @@ static int graph_sort(Ctx* c, SortJob<K, V>& J, void* user_ws, hipStream_t s, dt
   key.gover = P.gover;
   key.tile = P.tile;
   key.ordered = J.o.ordered_ranks != 0;
+  key.merge_variant = J.o.merge_variant;
   key.cutoff = P.cutoff;
   const GPlan g = graph_plan(J, P);
   key.levels = g.levels;
@@ -983,6 +988,7 @@ static int prepare_job(K* keys, V* vals, size_t n, const uint64_t* seg, size_t n
   if (o.mode < 0 || o.mode > 2) return fail(DTSORT_EINVAL, "unknown mode");
   if (o.digit_bits < 0 || o.digit_bits > GMAX) return fail(DTSORT_EINVAL, "digit_bits out of range");
   if (o.tile_shape < 0 || o.tile_shape > 6) return fail(DTSORT_EINVAL, "tile_shape out of range");
+  if (o.merge_variant < MV_GATHER || o.merge_variant > MV_NONE) return fail(DTSORT_EINVAL, "unknown merge_variant");
   if (o.graph && (o.mode == DTSORT_MODE_LEARNED || o.profile))
     return fail(DTSORT_EINVAL, "graph mode does not combine with LEARNED mode or profiling");
   if (seg && n_seg >= (1ull << 31)) return fail(DTSORT_EINVAL, "too many segments");

@@ -12,6 +12,8 @@
 // zone is written to tgt(P).  For records with values, when dst(P) = tgt(P)
 // the heavy values are first copied ("spilled") to the same range of src(P),
 // which nothing else uses after P's distribution.
+#include <type_traits>
+
 #include "block_sort.hpp"
 #include "launch.hpp"
 
@@ -294,7 +296,8 @@ __global__ __launch_bounds__(256) void k_children(LevelArgs a) {
     const uint32_t c0 = st[lid + 1] - s0;
     int ctgt = t.tgt;
     if (m > 0) {
-      ctgt = 1 - t.tgt;
+      const bool in_tgt = zone_in_target(a.merge_variant);
+      ctgt = in_tgt ? t.tgt : 1 - t.tgt;
       const uint32_t zend = st[lid + m + 1];
       const uint32_t zsize = zend - s0;
       Merge& g = mg[k];
@@ -311,10 +314,12 @@ __global__ __launch_bounds__(256) void k_children(LevelArgs a) {
       g.out_buf = (uint8_t)t.tgt;
       g.g = t.gamma;
       spieces[k] = 0;
-      if (HV && dst == t.tgt && zsize > c0) {
-        // heavy values would be overwritten by the gather: copy them to src first
+      if (in_tgt ? (dst != t.tgt && zsize > c0) : (HV && dst == t.tgt && zsize > c0)) {
+        // gather: heavy values would be overwritten by the gather, so they are
+        // copied to src first.  Zone-in-target variants: the heavy runs are
+        // copied next to the light run in the target buffer.
         spieces[k] = pieces_of(zsize - c0);
-        g.hv_buf = (uint8_t)t.src;
+        g.hv_buf = (uint8_t)(in_tgt ? t.tgt : t.src);
         sslot[k] = reserve_local(&r, KD_SPILL, spieces[k]);
         atomicAdd(&r.st_copy, (unsigned long long)(zsize - c0));
       }
@@ -378,7 +383,7 @@ __global__ __launch_bounds__(256) void k_children(LevelArgs a) {
         l.size = min(COPY_PIECE, zsize - p);
         l.bits = 0;
         l.from = (uint8_t)dst;
-        l.to = (uint8_t)t.src;
+        l.to = g.hv_buf;
         l.pad = 0;
         a.spills[si + q] = l;
       }
@@ -607,13 +612,232 @@ __global__ __launch_bounds__(256) void k_merge_gather(const Merge* m, const uint
   }
 }
 
+// ---- PLMerge-style variant (the paper's baseline in its merge study): a
+// general parallel merge of two sorted runs, X = the zone's light run and
+// Y = its heavy runs (both read from the target buffer, where the zone lies
+// contiguously), by merge path, into the partner buffer; a second launch
+// copies the merged zone back.  No use is made of the heavy runs' constant
+// keys.  Light and heavy keys are never equal, so the merge order is unique.
+template <typename K>
+__device__ inline uint32_t merge_path(const K* X, uint32_t nx, const K* Y, uint32_t ny, uint32_t q) {
+  // number of X records among the first q outputs
+  uint32_t lo = q > ny ? q - ny : 0u, hi = min(q, nx);
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (X[mid] < Y[q - mid - 1u])
+      lo = mid + 1u;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+template <typename K, typename V>
+__global__ __launch_bounds__(256) void k_plmerge(const Merge* m, const uint2* munits, const uint32_t* count,
+                                                 uint32_t cap, const uint8_t* tab, Bufs<K, V> bf) {
+  constexpr bool HV = HasVal<V>::value;
+  constexpr int PER = MERGE_TILE / 256;  // outputs per thread
+  __shared__ K sk[MERGE_TILE];
+  __shared__ typename std::conditional<HV, V, uint8_t>::type sv[HV ? MERGE_TILE : 1];
+  __shared__ uint32_t sx[2];
+  const uint32_t n_units = min(*count, cap);
+  for (uint32_t ui = blockIdx.x; ui < n_units; ui += gridDim.x) {
+    const uint2 u = munits[ui];
+    const Merge mg = m[u.x];
+    const SlotLayout sl = slot_layout(mg.g, false);
+    const uint32_t* st = (const uint32_t*)(tab + mg.tab_off + sl.starts);
+    const uint32_t zsize = st[mg.bstart + mg.m + 1] - st[mg.bstart];
+    const uint32_t nx = mg.b0, ny = zsize - nx;
+    const K* X = bf.k[mg.out_buf] + mg.zone_off;
+    const K* Y = X + nx;
+    const uint32_t q0 = u.y * MERGE_TILE;
+    const uint32_t qn = min((uint32_t)MERGE_TILE, zsize - q0);
+    if (threadIdx.x == 0) sx[0] = merge_path<K>(X, nx, Y, ny, q0);
+    if (threadIdx.x == 64) sx[1] = merge_path<K>(X, nx, Y, ny, q0 + qn);
+    __syncthreads();
+    const uint32_t x0 = sx[0], x1 = sx[1];
+    const uint32_t cx = x1 - x0;  // X records of this unit; then qn - cx Y records
+    const uint32_t y0 = q0 - x0;
+    for (uint32_t i = threadIdx.x; i < qn; i += 256) {
+      sk[i] = i < cx ? X[x0 + i] : Y[y0 + (i - cx)];
+      if constexpr (HV) {
+        const V* vx = bf.v[mg.out_buf] + mg.zone_off;
+        sv[i] = i < cx ? vx[x0 + i] : vx[nx + y0 + (i - cx)];
+      }
+    }
+    __syncthreads();
+    // each thread merges PER consecutive outputs of the unit from LDS
+    const uint32_t o0 = min((uint32_t)threadIdx.x * PER, qn);
+    const uint32_t o1 = min(o0 + PER, qn);
+    uint32_t i = merge_path<K>(sk, cx, sk + cx, qn - cx, o0);
+    uint32_t j = o0 - i;
+    K* ok = bf.k[1 - mg.out_buf] + mg.zone_off + q0;
+    for (uint32_t q = o0; q < o1; ++q) {
+      const bool takex = j >= qn - cx || (i < cx && sk[i] < sk[cx + j]);
+      const uint32_t src = takex ? i : cx + j;
+      ok[q] = sk[src];
+      if constexpr (HV) (bf.v[1 - mg.out_buf] + mg.zone_off + q0)[q] = sv[src];
+      if (takex)
+        ++i;
+      else
+        ++j;
+    }
+    __syncthreads();
+  }
+}
+
+// Copy of every merged unit back from the partner buffer to the target.
+template <typename K, typename V>
+__global__ __launch_bounds__(256) void k_plmerge_back(const Merge* m, const uint2* munits, const uint32_t* count,
+                                                      uint32_t cap, const uint8_t* tab, Bufs<K, V> bf) {
+  const uint32_t n_units = min(*count, cap);
+  for (uint32_t ui = blockIdx.x; ui < n_units; ui += gridDim.x) {
+    const uint2 u = munits[ui];
+    const Merge mg = m[u.x];
+    const SlotLayout sl = slot_layout(mg.g, false);
+    const uint32_t* st = (const uint32_t*)(tab + mg.tab_off + sl.starts);
+    const uint32_t zsize = st[mg.bstart + mg.m + 1] - st[mg.bstart];
+    const uint32_t q0 = u.y * MERGE_TILE;
+    const uint32_t qn = min((uint32_t)MERGE_TILE, zsize - q0);
+    const uint64_t o = mg.zone_off + q0;
+    copy_range<K>(bf.k[mg.out_buf] + o, bf.k[1 - mg.out_buf] + o, qn);
+    if constexpr (HasVal<V>::value) copy_range<V>(bf.v[mg.out_buf] + o, bf.v[1 - mg.out_buf] + o, qn);
+  }
+}
+
+// ---- Alg. 3 literally, one workgroup per zone: the zone lies contiguously
+// in its target buffer A (light run B0, then the heavy runs B1..Bm); the
+// partner buffer's range of the zone serves as the temporary array T.
+// Buckets are moved one after the other, each by all threads.
+template <typename T>
+__device__ inline void flip_range(T* a, uint32_t s, uint32_t e) {  // reverse a[s, e)
+  const uint32_t len = e - s;
+  for (uint32_t j = threadIdx.x; j < len / 2; j += blockDim.x) {
+    const T x = a[s + j];
+    a[s + j] = a[e - 1 - j];
+    a[e - 1 - j] = x;
+  }
+}
+
+template <typename T>
+__device__ inline void move_range(T* a, uint32_t from, uint32_t to, uint32_t len) {  // disjoint ranges
+  for (uint32_t j = threadIdx.x; j < len; j += blockDim.x) a[to + j] = a[from + j];
+}
+
+template <typename K, typename V>
+__device__ inline void zone_flip(Bufs<K, V>& bf, int buf, uint64_t zo, uint32_t s, uint32_t e) {
+  flip_range<K>(bf.k[buf] + zo, s, e);
+  if constexpr (HasVal<V>::value) flip_range<V>(bf.v[buf] + zo, s, e);
+}
+
+template <typename K, typename V>
+__device__ inline void zone_move(Bufs<K, V>& bf, int from_buf, uint64_t from, int to_buf, uint64_t to, uint32_t len) {
+  const K* ks = bf.k[from_buf] + from;
+  K* kd = bf.k[to_buf] + to;
+  for (uint32_t j = threadIdx.x; j < len; j += blockDim.x) kd[j] = ks[j];
+  if constexpr (HasVal<V>::value) {
+    const V* vs = bf.v[from_buf] + from;
+    V* vd = bf.v[to_buf] + to;
+    for (uint32_t j = threadIdx.x; j < len; j += blockDim.x) vd[j] = vs[j];
+  }
+}
+
+template <typename K, typename V>
+__global__ __launch_bounds__(1024) void k_merge_inplace(const Merge* m, const uint32_t* count, uint32_t cap,
+                                                        const uint8_t* tab, Bufs<K, V> bf) {
+  const uint32_t n_merges = min(*count, cap);
+  for (uint32_t mi = blockIdx.x; mi < n_merges; mi += gridDim.x) {
+    const Merge mg = m[mi];
+    const SlotLayout sl = slot_layout(mg.g, false);
+    const uint8_t* slot = tab + mg.tab_off;
+    const uint32_t* P = (const uint32_t*)(slot + sl.light) + mg.hbase;  // final starts p_i (k_merge_pos)
+    const uint32_t* hs = (const uint32_t*)(slot + sl.starts) + mg.bstart + 1;  // heavy bucket starts, task-relative
+    const uint32_t M = mg.m, b0 = mg.b0;
+    const uint32_t zsize = hs[M] - hs[-1];
+    const uint32_t hbeg = hs[0];  // task-relative start of the first heavy run
+    const int A = mg.out_buf, Tb = 1 - mg.out_buf;
+    const uint64_t zo = mg.zone_off;
+    // lb_i = lower_bound(B0, h_i) = p_i - (heavy records before bucket i)
+    auto lb = [&](uint32_t i) { return P[i] - (hs[i] - hbeg); };
+    if (b0 <= zsize - b0) {
+      // more heavy records: B0 out to T, heavy runs to their places one by one
+      zone_move<K, V>(bf, A, zo, Tb, zo, b0);
+      __syncthreads();
+      uint32_t s = b0;  // current start of B_i (heavy runs have not moved yet)
+      for (uint32_t i = 0; i < M; ++i) {
+        const uint32_t sz = hs[i + 1] - hs[i], p = P[i];
+        if (p + sz > s) {  // the destination overlaps the bucket itself: two flips
+          zone_flip<K, V>(bf, A, zo, s, s + sz);
+          __syncthreads();
+          zone_flip<K, V>(bf, A, zo, p, s + sz);
+        } else {
+          zone_move<K, V>(bf, A, zo + s, A, zo + p, sz);
+        }
+        __syncthreads();
+        s += sz;
+      }
+      // light record l goes after the heavy runs whose keys are below its key
+      for (uint32_t l = threadIdx.x; l < b0; l += blockDim.x) {
+        uint32_t lo = 0, n = M;  // heavy buckets with lb_i <= l
+        while (n > 0) {
+          const uint32_t half = n >> 1;
+          if (lb(lo + half) <= l) {
+            lo += half + 1;
+            n -= half + 1;
+          } else {
+            n = half;
+          }
+        }
+        const uint32_t d = l + (hs[lo] - hbeg);
+        bf.k[A][zo + d] = bf.k[Tb][zo + l];
+        if constexpr (HasVal<V>::value) bf.v[A][zo + d] = bf.v[Tb][zo + l];
+      }
+    } else {
+      // more light records: heavy runs out to T, light blocks to their places
+      // from the last one back, heavy runs back from T
+      zone_move<K, V>(bf, A, zo + b0, Tb, zo + b0, zsize - b0);
+      __syncthreads();
+      for (uint32_t k = M + 1; k-- > 0;) {
+        // light block k lies after heavy runs 0..k-1: B0[lb_{k-1}, lb_k)
+        const uint32_t s = k == 0 ? 0u : lb(k - 1);
+        const uint32_t e = k == M ? b0 : lb(k);
+        const uint32_t h = hs[k] - hbeg;  // heavy records before the block
+        if (e > s && h > 0) {
+          if (h < e - s) {  // overlap: block and the free slots after it, two flips
+            zone_flip<K, V>(bf, A, zo, s, e);
+            __syncthreads();
+            zone_flip<K, V>(bf, A, zo, s, e + h);
+          } else {
+            zone_move<K, V>(bf, A, zo + s, A, zo + s + h, e - s);
+          }
+        }
+        __syncthreads();
+      }
+      for (uint32_t i = 0; i < M; ++i)
+        zone_move<K, V>(bf, Tb, zo + b0 + (hs[i] - hbeg), A, zo + P[i], hs[i + 1] - hs[i]);
+    }
+    __syncthreads();
+  }
+}
+
 template <typename K, typename V>
 void launch_merge(const Merge* m, const uint32_t* n_merges, uint32_t merge_cap, uint32_t merge_grid,
                   const uint2* munits, const uint32_t* n_munits, uint32_t munit_cap, uint32_t munit_grid,
-                  uint8_t* tab, Bufs<K, V> b, hipStream_t s) {
-  if (merge_grid == 0 || merge_cap == 0) return;
+                  uint8_t* tab, Bufs<K, V> b, int variant, hipStream_t s) {
+  if (merge_grid == 0 || merge_cap == 0 || variant == MV_NONE) return;
+  if (variant == MV_PLMERGE) {
+    if (munit_grid == 0 || munit_cap == 0) return;
+    hipLaunchKernelGGL((k_plmerge<K, V>), dim3(munit_grid), dim3(256), 0, s, m, munits, n_munits, munit_cap, tab, b);
+    hipLaunchKernelGGL((k_plmerge_back<K, V>), dim3(munit_grid), dim3(256), 0, s, m, munits, n_munits, munit_cap, tab,
+                       b);
+    return;
+  }
   hipLaunchKernelGGL((k_merge_pos<K>), dim3(merge_grid), dim3(64), 0, s, m, n_merges, merge_cap, tab,
                      (const K*)b.k[0], (const K*)b.k[1]);
+  if (variant == MV_INPLACE) {
+    hipLaunchKernelGGL((k_merge_inplace<K, V>), dim3(merge_grid), dim3(1024), 0, s, m, n_merges, merge_cap, tab, b);
+    return;
+  }
   if (munit_grid == 0 || munit_cap == 0) return;
   hipLaunchKernelGGL((k_merge_gather<K, V>), dim3(munit_grid), dim3(256), 0, s, m, munits, n_munits, munit_cap, tab,
                      b);
@@ -688,7 +912,7 @@ template void launch_root<uint64_t>(Task*, LevelCounters*, uint64_t, int, int, h
   template void launch_seed_segments<K, V>(const LevelArgs&, const uint64_t*, uint32_t, uint64_t, hipStream_t); \
   template void launch_copy<K, V>(const Leaf*, const uint32_t*, uint32_t, uint32_t, Bufs<K, V>, hipStream_t); \
   template void launch_merge<K, V>(const Merge*, const uint32_t*, uint32_t, uint32_t, const uint2*,        \
-                                   const uint32_t*, uint32_t, uint32_t, uint8_t*, Bufs<K, V>, hipStream_t);
+                                   const uint32_t*, uint32_t, uint32_t, uint8_t*, Bufs<K, V>, int, hipStream_t);
 DTS_INST(uint32_t, NoVal)
 DTS_INST(uint64_t, NoVal)
 DTS_INST(uint64_t, uint64_t)

@@ -41,9 +41,17 @@ struct LevelArgs {
   int key_bits;
   int tile;  // scatter tile shape (0..4, see launch_distribute)
   int ordered;  // keys without values: keep equal-bucket keys in input order (stable ranks)
+  int merge_variant;  // MergeVariant: how zones with heavy keys are merged
   uint32_t grid_tasks;  // launch grid of the per-task kernels
   uint32_t grid_units;  // launch grid of the per-unit kernels
 };
+
+// Implementations of Step 4 (the dovetail merge) for the paper's merge study.
+enum MergeVariant : int { MV_GATHER = 0, MV_PLMERGE = 1, MV_INPLACE = 2, MV_NONE = 3 };
+// Variants that work on the zone laid out contiguously in its target buffer
+// (the light run sorted there, the heavy runs copied there when the
+// distribution left them in the other buffer).
+__host__ __device__ inline bool zone_in_target(int v) { return v == MV_PLMERGE || v == MV_INPLACE; }
 
 // Grid of the persistent (grid-stride) launches: workgroups per compute unit
 // times the compute units of the current device.
@@ -115,10 +123,11 @@ void launch_copy(const Leaf* items, const uint32_t* count, uint32_t cap, uint32_
 void launch_merge_units(const Merge* m, const uint32_t* count, uint32_t cap, uint32_t grid, uint2* munits,
                         hipStream_t s);
 
+// Merges of one level's zones with the given MergeVariant (MV_NONE: nothing).
 template <typename K, typename V>
 void launch_merge(const Merge* m, const uint32_t* n_merges, uint32_t merge_cap, uint32_t merge_grid,
                   const uint2* munits, const uint32_t* n_munits, uint32_t munit_cap, uint32_t munit_grid,
-                  uint8_t* tab, Bufs<K, V> b, hipStream_t s);
+                  uint8_t* tab, Bufs<K, V> b, int variant, hipStream_t s);
 
 // Learned partitioner (k_mlp.hip).
 int mlp_loss_grad(const float* p, const float* x, const float* y, uint32_t n, float* grad, float* loss, float* part,

@@ -308,12 +308,12 @@ int dtsort_step_dtmerge_u64(const uint64_t* b0_keys, const uint64_t* b0_values, 
     b.k[1] = out_keys;
     b.v[0] = zv;
     b.v[1] = out_values;
-    launch_merge<uint64_t, uint64_t>(dm, dcount, 1, 1, mu, dcount + 1, nunits, nunits, tab, b, s);
+    launch_merge<uint64_t, uint64_t>(dm, dcount, 1, 1, mu, dcount + 1, nunits, nunits, tab, b, MV_GATHER, s);
   } else {
     Bufs<uint64_t, NoVal> b;
     b.k[0] = zk;
     b.k[1] = out_keys;
-    launch_merge<uint64_t, NoVal>(dm, dcount, 1, 1, mu, dcount + 1, nunits, nunits, tab, b, s);
+    launch_merge<uint64_t, NoVal>(dm, dcount, 1, 1, mu, dcount + 1, nunits, nunits, tab, b, MV_GATHER, s);
   }
   SCHK(hipGetLastError());
   SCHK(hipStreamSynchronize(s));

@@ -127,7 +127,7 @@ def test_tune_table_format():
         rows.append(v)
     # every layout the entry points take has a row
     keys = {(r[0], r[1], r[2]) for r in rows}
-    for k in ((4, 0, 0), (8, 0, 0), (8, 8, 0), (4, 0, 1)):
+    for k in ((4, 0, 0), (8, 0, 0), (8, 8, 0), (4, 4, 0), (4, 0, 1)):
         assert k in keys
 
 

@@ -454,7 +454,8 @@ MERGE_STUDY = (("unif", 1000), ("exp", 1), ("exp", 10), ("zipf", 0.6), ("zipf", 
 def run_merge_study(args):
     """The paper's merge study (Section 6.3, Fig. scale c-d): for its seven
     distributions (Unif-10^3, and the lightest and heaviest of Exp, Zipf and
-    BExp), sorts of n records with each Step 4 implementation and with none
+    BExp), sorts of n records with each Step 4 implementation, with
+    dovetailing during distribution (no merge step at all) and with no merge
     (the time of the other steps); the merge share is (t - t_none) / t."""
     import torch
 
@@ -465,7 +466,8 @@ def run_merge_study(args):
     n = int(args.n)
     steps = max(1, min(args.steps, 5))
     variants = (("dtmerge_gather", dt.MERGE_GATHER), ("plmerge", dt.MERGE_PLMERGE),
-                ("dtmerge_inplace", dt.MERGE_INPLACE), ("no_merge", dt.MERGE_NONE))
+                ("dtmerge_inplace", dt.MERGE_INPLACE), ("split_at_distribution", dt.MERGE_SPLIT),
+                ("no_merge", dt.MERGE_NONE))
     res = {}
     for bits in (32, 64):
         vt = torch.int32 if bits == 32 else torch.int64
@@ -490,12 +492,13 @@ def run_merge_study(args):
                     row["merged_records"] = int(st.records_merged)
                     row["merges"] = int(st.merges)
             t0 = row["no_merge"]["ms"]
-            for vname, _ in variants[:3]:
+            for vname, _ in variants[:4]:
                 t = row[vname]["ms"]
                 row[vname]["merge_ms"] = round(t - t0, 3)
                 row[vname]["merge_share"] = round((t - t0) / t, 3)
             row["plmerge_over_gather"] = round(row["plmerge"]["ms"] / row["dtmerge_gather"]["ms"], 3)
             row["inplace_over_gather"] = round(row["dtmerge_inplace"]["ms"] / row["dtmerge_gather"]["ms"], 3)
+            row["split_over_gather"] = round(row["split_at_distribution"]["ms"] / row["dtmerge_gather"]["ms"], 3)
             res[name] = row
         del k, v, kw, vw
         torch.cuda.empty_cache()
@@ -546,6 +549,12 @@ def run_extra(dt, W, torch, np, n, args, opts):
         st = dt.Stats()
         one(name, lambda: dt.sort_pairs_u64(kw, vw, opts(stats=st)), k, kw, v, vw)
         res[name]["levels"] = int(st.levels)
+        res[name]["merged_records"] = int(st.records_merged)
+        # dovetailing during distribution: no merge step
+        ss = dt.Stats()
+        one(name + "_split", lambda: dt.sort_pairs_u64(kw, vw, opts(stats=ss, merge_variant=dt.MERGE_SPLIT)), k, kw,
+            v, vw)
+        res[name + "_split"].update(levels=int(ss.levels), merges=int(ss.merges), copied_records=int(ss.records_copied))
         if name.startswith("bexp"):
             # the learned partitioner on the input whose bit lengths are geometric
             sl = dt.Stats()

@@ -130,8 +130,13 @@ typedef struct dtsort_opts {
                                  out, heavy buckets moved one by one (two flips where a bucket overlaps its
                                  destination), the copied side moved back;
                              3 = no merge: zones with heavy keys are left unmerged, so the output is NOT
-                                 sorted (a timing knob for the other steps).
-                             Variants 0-2 give the same sorted output. */
+                                 sorted (a timing knob for the other steps);
+                             4 = dovetailing during distribution (a variant derived from Section 3.4):
+                                 each zone's light keys are split at its heavy keys into light sub-buckets
+                                 (at most 2^(digit bits - 2) heavy keys a subproblem, the ones filling the
+                                 most subsample slots), so heavy buckets land in their final places and
+                                 no merge is needed (a learned root's zones still merge as in 0).
+                             Variants 0-2 and 4 give the same sorted output. */
   void* workspace;        /* optional device buffer for the ping-pong partner (see dtsort_workspace_bytes) */
   size_t workspace_bytes;
   dtsort_stats* stats;    /* optional host pointer */

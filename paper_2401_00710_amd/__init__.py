@@ -10,12 +10,12 @@ from __future__ import annotations
 import ctypes as C
 
 from . import _lib
-from ._lib import (MERGE_GATHER, MERGE_INPLACE, MERGE_NONE, MERGE_PLMERGE, MODE_LEARNED, MODE_PLAIN,  # noqa: F401
-                   MODE_SAMPLING, DTSortError, Opts, Stats)
+from ._lib import (MERGE_GATHER, MERGE_INPLACE, MERGE_NONE, MERGE_PLMERGE, MERGE_SPLIT, MODE_LEARNED,  # noqa: F401
+                   MODE_PLAIN, MODE_SAMPLING, DTSortError, Opts, Stats)
 
 __all__ = ["sort_u32", "sort_u64", "sort_pairs_u64", "sort_pairs_u32", "sort_segmented", "sort_segmented_noalloc", "copy_u32", "make_opts", "Stats",
            "MODE_SAMPLING", "MODE_PLAIN", "MODE_LEARNED", "MERGE_GATHER", "MERGE_PLMERGE", "MERGE_INPLACE",
-           "MERGE_NONE", "DTSortError"]
+           "MERGE_NONE", "MERGE_SPLIT", "DTSortError"]
 
 
 def make_opts(seed=0, key_bits=0, mode=MODE_SAMPLING, digit_bits=0, lds_cutoff=0, tuned=0,

@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(_HERE, "libdtsort.so")
 
 OK, EINVAL, ENOMEM, EWORKSPACE, EHIP, EINTERNAL = 0, -1, -2, -3, -4, -5
 MODE_SAMPLING, MODE_PLAIN, MODE_LEARNED = 0, 1, 2
-MERGE_GATHER, MERGE_PLMERGE, MERGE_INPLACE, MERGE_NONE = 0, 1, 2, 3
+MERGE_GATHER, MERGE_PLMERGE, MERGE_INPLACE, MERGE_NONE, MERGE_SPLIT = 0, 1, 2, 3, 4
 
 
 class Stats(C.Structure):

@@ -988,7 +988,7 @@ static int prepare_job(K* keys, V* vals, size_t n, const uint64_t* seg, size_t n
   if (o.mode < 0 || o.mode > 2) return fail(DTSORT_EINVAL, "unknown mode");
   if (o.digit_bits < 0 || o.digit_bits > GMAX) return fail(DTSORT_EINVAL, "digit_bits out of range");
   if (o.tile_shape < 0 || o.tile_shape > 6) return fail(DTSORT_EINVAL, "tile_shape out of range");
-  if (o.merge_variant < MV_GATHER || o.merge_variant > MV_NONE) return fail(DTSORT_EINVAL, "unknown merge_variant");
+  if (o.merge_variant < MV_GATHER || o.merge_variant > MV_SPLIT) return fail(DTSORT_EINVAL, "unknown merge_variant");
   if (o.graph && (o.mode == DTSORT_MODE_LEARNED || o.profile))
     return fail(DTSORT_EINVAL, "graph mode does not combine with LEARNED mode or profiling");
   if (seg && n_seg >= (1ull << 31)) return fail(DTSORT_EINVAL, "too many segments");

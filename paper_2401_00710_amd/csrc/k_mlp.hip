@@ -601,7 +601,7 @@ __global__ __launch_bounds__(1024) void k_judge_apply(Task* task, uint8_t* tab, 
     gL[z] = z + lo;
   }
   if (threadIdx.x == 0) {
-    t.flags |= TF_LEARNED;
+    t.flags = (uint8_t)((t.flags & ~TF_SPLIT) | TF_LEARNED);
     t.w = (uint8_t)g;
     t.shift = 0;
     t.top = t.hi;

@@ -32,6 +32,7 @@ __global__ __launch_bounds__(T, T == 512 ? 4 : 1) void k_plan(LevelArgs a, const
   __shared__ uint32_t cnt[bsort_cnt_words<T>()];
   __shared__ K red[2 * (T / WAVE)];
   __shared__ uint32_t hz[1 << (GMAX - 1)];
+  __shared__ uint32_t hc[1 << (GMAX - 1)];  // subsample slots each heavy key fills
   __shared__ uint32_t tmp[T / WAVE + 1];
   __shared__ int s_top, s_w, s_shift;
   __shared__ uint32_t s_flag;
@@ -41,6 +42,7 @@ __global__ __launch_bounds__(T, T == 512 ? 4 : 1) void k_plan(LevelArgs a, const
   Task& tr = a.tasks[ti];
   const Task t = tr;
   if (t.flags & TF_LEARNED) continue;  // planned by the learned-partitioner step
+  const bool split = a.merge_variant == MV_SPLIT;
   const int g = t.gamma;
   const int hi = t.hi;
   const SlotLayout sl = slot_layout(g, false);
@@ -115,7 +117,37 @@ __global__ __launch_bounds__(T, T == 512 ? 4 : 1) void k_plan(LevelArgs a, const
           gH[idx] = (uint64_t)kj;
           const K low = kj & mask_below<K>(hi);
           hz[idx] = (uint32_t)(shr<K>(low, s_shift) & (K)((1u << s_w) - 1u));
+          uint32_t c = 2;
+          while (j + c < nsub && sk[(j + c) * ts] == kj) ++c;
+          hc[idx] = c;
         }
+        __syncthreads();
+      }
+      // The split layout has two buckets per heavy key; to stay within the
+      // bucket capacity of the digit width it keeps at most 2^(g-2) heavy
+      // keys (none for 1-bit digits): those filling the most subsample slots
+      // (ties: smaller key).
+      const uint32_t cap = g >= 2 ? 1u << (g - 2) : 0u;
+      if (split && nh > cap) {
+        // nh <= 2^(g-1) <= T: one candidate per thread
+        const uint32_t i = threadIdx.x;
+        uint32_t keep = 0, z0 = 0;
+        uint64_t hk = 0;
+        if (i < nh) {
+          uint32_t rank = 0;
+          for (uint32_t j = 0; j < nh; ++j) rank += (hc[j] > hc[i] || (hc[j] == hc[i] && j < i)) ? 1u : 0u;
+          keep = rank < cap ? 1u : 0u;
+          hk = gH[i];
+          z0 = hz[i];
+        }
+        __syncthreads();
+        uint32_t total;
+        const uint32_t idx = block_excl_scan<T>(keep, tmp, &total);
+        if (keep) {
+          gH[idx] = hk;
+          hz[idx] = z0;
+        }
+        nh = total;
         __syncthreads();
       }
     }
@@ -135,14 +167,15 @@ __global__ __launch_bounds__(T, T == 512 ? 4 : 1) void k_plan(LevelArgs a, const
         n = half;
       }
     }
-    gL[z] = z + lo;
+    gL[z] = z + (split ? 2u : 1u) * lo;
   }
   if (threadIdx.x == 0) {
     tr.w = (uint8_t)w;
     tr.shift = (uint8_t)s_shift;
     tr.top = (uint8_t)s_top;
     tr.n_heavy = (uint16_t)nh;
-    tr.n_buckets = (uint16_t)(zones + nh + 1);
+    tr.n_buckets = (uint16_t)(zones + (split ? 2u : 1u) * nh + 1);
+    if (split) tr.flags = (uint8_t)(t.flags | TF_SPLIT);
   }
   __syncthreads();
   }

@@ -281,6 +281,51 @@ __global__ __launch_bounds__(256) void k_children(LevelArgs a) {
   // wrong buffer, the whole task range is copied as one item list instead of
   // bucket by bucket (the buckets are adjacent and in order).
   const bool whole_copy = !learned && t.shift == 0 && t.n_heavy == 0 && st[ob + 1] == st[ob] && dst != t.tgt;
+  if ((t.flags & TF_SPLIT) && t.n_heavy != 0 && !learned) {
+    // Split layout: every light sub-bucket is a child with the task's target
+    // (no merge follows); heavy buckets are finished where they landed.
+    constexpr int SPT = (nb_cap(GMAX) + 255) / 256;  // buckets per thread
+    Child cs[SPT + 1];
+#pragma unroll
+    for (int k = 0; k < SPT; ++k) {
+      cs[k].kind = -1;
+      const uint32_t b = threadIdx.x + 256u * k;
+      if (b >= ob) continue;
+      uint32_t lo = 0, n = zones;  // the zone of b: the last z with L[z] <= b
+      while (n > 0) {
+        const uint32_t half = n >> 1;
+        if (L[lo + half] <= b) {
+          lo += half + 1;
+          n -= half + 1;
+        } else {
+          n = half;
+        }
+      }
+      const bool heavy = ((b - L[lo - 1u]) & 1u) != 0u;
+      const uint32_t c = st[b + 1] - st[b];
+      if (heavy && c) atomicAdd(&r.st_heavy, (unsigned long long)c);
+      cs[k] = plan_child(a, &r, t.off + st[b], c, heavy ? 0 : t.shift, dst, t.tgt, false);
+    }
+    cs[SPT].kind = -1;
+    if (threadIdx.x == 0) {
+      const uint32_t c = st[ob + 1] - st[ob];
+      if (c) atomicAdd(&r.st_over, (unsigned long long)c);
+      cs[SPT] = plan_child(a, &r, t.off + st[ob], c, t.hi, dst, t.tgt, true);
+    }
+    __syncthreads();
+    reserve_global(a, &r);
+    if (threadIdx.x == 2 * WAVE) {
+      atomicAdd(&a.ctr->st_heavy_keys, (unsigned long long)t.n_heavy);
+      atomicAdd(&a.ctr->st_tasks, 1ull);
+      atomicAdd(&a.ctr->st_distributed, (unsigned long long)t.size);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k <= SPT; ++k)
+      if (cs[k].kind >= 0) write_child(a, cs[k], r.base[cs[k].kind], t.n_root, t.level + 1, a.g_override);
+    __syncthreads();
+    continue;
+  }
   Child ch[ZPT + 1];
   Merge mg[ZPT];
   uint32_t mslot[ZPT], uslot[ZPT], sslot[ZPT], spieces[ZPT];

@@ -47,7 +47,11 @@ struct LevelArgs {
 };
 
 // Implementations of Step 4 (the dovetail merge) for the paper's merge study.
-enum MergeVariant : int { MV_GATHER = 0, MV_PLMERGE = 1, MV_INPLACE = 2, MV_NONE = 3 };
+// MV_SPLIT: no merge at all; every zone's light keys are split at its heavy
+// keys during the distribution (the split bucket layout, TF_SPLIT), so heavy
+// buckets land in their final places.  Zones of a learned root still merge
+// (as MV_GATHER).
+enum MergeVariant : int { MV_GATHER = 0, MV_PLMERGE = 1, MV_INPLACE = 2, MV_NONE = 3, MV_SPLIT = 4 };
 // Variants that work on the zone laid out contiguously in its target buffer
 // (the light run sorted there, the heavy runs copied there when the
 // distribution left them in the other buffer).

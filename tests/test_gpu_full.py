@@ -64,17 +64,21 @@ def _check_keys(inp: np.ndarray, out: np.ndarray, seed: int):
     assert np.array_equal(out[qs], ref)
 
 
-@pytest.mark.parametrize("kind", ["uniform", "zipf1"])
-def test_full_u32(kind):
+@pytest.mark.parametrize("kind,mv", [("uniform", 0), ("zipf1", 0), ("zipf1", dt.MERGE_SPLIT)])
+def test_full_u32(kind, mv):
+    """mv = MERGE_SPLIT: dovetailing during distribution (no merges)."""
     require_gpu()
-    say(f"full u32 {kind}: generate")
+    say(f"full u32 {kind} merge_variant={mv}: generate")
     if kind == "uniform":
         src = W.uniform_u32(N, seed=0, device="cuda").to(torch.int32)
     else:
         src = W.zipf_u32(N, 1.0, N, seed=0, device="cuda").to(torch.int32)
     inp = _host(src, np.uint32)
     say("  sort")
-    dt.sort_u32(src, dt.make_opts(tuned=1))
+    st = dt.Stats()
+    dt.sort_u32(src, dt.make_opts(tuned=1, merge_variant=mv, stats=st))
+    if mv == dt.MERGE_SPLIT:
+        assert st.merges == 0 and st.heavy_keys > 0
     torch.cuda.synchronize()
     out = _host(src, np.uint32)
     del src
@@ -102,8 +106,10 @@ def test_full_u32_beyond_2p31():
     _check_keys(inp, out, 3)
 
 
-@pytest.mark.parametrize("kind,mode", [("exp", "sampling"), ("bexp", "sampling"), ("bexp", "learned")])
+@pytest.mark.parametrize("kind,mode", [("exp", "sampling"), ("bexp", "sampling"), ("bexp", "learned"),
+                                       ("bexp", "split")])
 def test_full_pairs_u64(kind, mode):
+    """mode "split": sampling with dovetailing during distribution."""
     require_gpu()
     say(f"full pairs {kind} {mode}: generate")
     k = (W.exponential_keys(N, 1e-5, seed=0, device="cuda") if kind == "exp"
@@ -113,8 +119,11 @@ def test_full_pairs_u64(kind, mode):
     say("  sort")
     st = dt.Stats()
     m = dt.MODE_LEARNED if mode == "learned" else dt.MODE_SAMPLING
-    dt.sort_pairs_u64(k, v, dt.make_opts(tuned=1, mode=m, stats=st))
+    mv = dt.MERGE_SPLIT if mode == "split" else dt.MERGE_GATHER
+    dt.sort_pairs_u64(k, v, dt.make_opts(tuned=1, mode=m, merge_variant=mv, stats=st))
     torch.cuda.synchronize()
+    if mode == "split":
+        assert st.merges == 0 and st.heavy_keys > 0
     if mode == "learned":
         # the benchmark reports this configuration with the model's zones in use
         say(f"  learned_used={st.learned_used} balance {st.learned_balance:.2f} vs {st.sampling_balance:.2f}")

@@ -2,7 +2,9 @@
 6.3, Fig. scale c-d): the dovetail merge as one gather (default), a general
 merge-path merge of each zone through the partner buffer (PLMerge-style) and
 Alg. 3 literally (smaller side copied out, heavy buckets moved one by one
-with two flips where a bucket overlaps its destination).  All three must give
+with two flips where a bucket overlaps its destination); and dovetailing
+during distribution (each zone's light keys split at its heavy keys, no
+merge).  All four must give
 the oracle's stable order exactly; the no-merge knob (a timing aid, not a
 sort) must run the same recursion without Step 4."""
 import numpy as np
@@ -17,7 +19,7 @@ from tests._seeds import seed_of
 
 pytestmark = pytest.mark.gpu
 
-VARIANTS = [dt.MERGE_GATHER, dt.MERGE_PLMERGE, dt.MERGE_INPLACE]
+VARIANTS = [dt.MERGE_GATHER, dt.MERGE_PLMERGE, dt.MERGE_INPLACE, dt.MERGE_SPLIT]
 
 
 def _keys(kind, n, bits, seed):
@@ -87,10 +89,12 @@ def test_merge_variants_match_oracle(layout, kind):
             if gv is not None:
                 assert np.array_equal(gv, ev), f"variant {mv} {params}: values"
             merged.append((str(params), mv, st.merges, st.records_merged))
-    # the recursion does not depend on the merge implementation
+    # the recursion does not depend on the merge implementation; the split
+    # layout merges nothing
     for p in {m[0] for m in merged}:
-        rows = [m for m in merged if m[0] == p]
+        rows = [m for m in merged if m[0] == p and m[1] != dt.MERGE_SPLIT]
         assert len({(r[2], r[3]) for r in rows}) == 1, rows
+        assert all(m[2] == 0 for m in merged if m[0] == p and m[1] == dt.MERGE_SPLIT)
     if kind in ("zipf-1.5", "heavy_majority", "light_majority", "bexp-300"):
         assert max(m[2] for m in merged) > 0, "the case is meant to merge zones"
 
@@ -121,3 +125,34 @@ def test_no_merge_knob_runs_the_same_recursion():
     assert st.merges > 0
     for f in ("levels", "tasks", "records_distributed", "heavy_keys", "merges", "records_leaf_sorted"):
         assert getattr(st, f) == getattr(sg, f), f
+
+
+@pytest.mark.parametrize("digits", [1, 2, 3, 8, 9, 10])
+def test_split_layout_digit_widths(digits):
+    """Dovetailing during distribution at every digit width class: the heavy
+    cap 2^(g-2) (none at g = 1), the hash-table and binary-search lookups,
+    and the wide-digit kernel variants; keys and 64-bit pairs."""
+    require_gpu()
+    say(f"split layout digits={digits}")
+    for layout, kind in (("u32", "zipf-1.5"), ("pairs64", "heavy_majority"), ("pairs32", "bexp-300")):
+        bits = 64 if layout == "pairs64" else 32
+        k = _keys(kind, 400_009, bits, digits)
+        v = np.arange(k.size, dtype=np.uint32 if bits == 32 else np.uint64)
+        ek, ev = S.stable_sort_pairs(k, v)
+        gk, gv, st = _run(layout, k, merge_variant=dt.MERGE_SPLIT, digit_bits=digits, lds_cutoff=300)
+        assert np.array_equal(gk, ek), layout
+        if gv is not None:
+            assert np.array_equal(gv, ev), layout
+        assert st.merges == 0
+        if digits >= 2:
+            assert st.heavy_keys > 0
+
+
+def test_split_with_learned_root():
+    """A learned root keeps its merges; the levels below split."""
+    require_gpu()
+    k = W.mixture_u64(1 << 21, seed=4).numpy().view(np.uint64)
+    v = np.arange(k.size, dtype=np.uint64)
+    ek, ev = S.stable_sort_pairs(k, v)
+    gk, gv, st = _run("pairs64", k, merge_variant=dt.MERGE_SPLIT, mode=dt.MODE_LEARNED)
+    assert np.array_equal(gk, ek) and np.array_equal(gv, ev)

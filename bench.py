@@ -154,6 +154,9 @@ def main():
     ap.add_argument("--merge-study", action="store_true",
                     help="the paper's merge study (Section 6.3): seven distributions, 32+32 and 64+64 records, "
                          "the dovetail merge as a gather, PLMerge-style, Alg. 3 in place, and no merge")
+    ap.add_argument("--apps", action="store_true",
+                    help="the paper's applications (Section 6.2) on synthetic stand-ins: graph transpose of a "
+                         "power-law graph and Morton order of varying-density points")
     ap.add_argument("--once", default=None, metavar="WORKLOAD",
                     help="for profilers: generate WORKLOAD, sort it once (tuned), print its time and exit; one of "
                          + ", ".join(ONCE))
@@ -164,6 +167,8 @@ def main():
         return run_grid(args)
     if args.merge_study:
         return run_merge_study(args)
+    if args.apps:
+        return run_apps(args)
     if args.gpus != 1:
         print(json.dumps({"error": "the benchmark runs on one GPU; --gpus above 1 is not supported "
                                    "(the sort has no multi-GPU path)"}), flush=True)
@@ -505,6 +510,60 @@ def run_merge_study(args):
     print(json.dumps({"merge_study": "Section 6.3 merge study, records with value = index", "n": n,
                       "steps": steps, "timing": "median of steps after one warm-up, HIP events",
                       "instances": res}), flush=True)
+
+
+def run_apps(args):
+    """Graph transpose (CSR in, CSR out) of a synthetic power-law graph of
+    2^25 vertices and n edges (Zipf out-degrees s = 0.8, in-degrees s = 1),
+    and Morton order of n varying-density points in 2-D and 3-D: whole
+    application calls (preparation kernels + the 32+32-bit sort), median of
+    `steps` after one warm-up."""
+    import torch
+
+    import paper_2401_00710_amd as dt
+    import workloads as W
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    n = int(args.n)
+    steps = max(1, min(args.steps, 5))
+    o = dt.make_opts(tuned=1)
+    res = {}
+
+    def timed(fn):
+        ts = []
+        for i in range(steps + 1):
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            if i:
+                ts.append(e0.elapsed_time(e1))
+        return statistics.median(ts)
+    V = 1 << 25
+    log(f"graph: {V} vertices, {n} edges")
+    off, tgt = W.power_law_graph(V, n, s_out=0.8, s_in=1.0, seed=0, device=dev)
+    tgt = tgt.to(torch.int32)
+    ms = timed(lambda: dt.graph_transpose(off, tgt, V, opts=o))
+    indeg = torch.bincount(tgt.to(torch.int64), minlength=V)
+    res["graph_transpose_powerlaw"] = {"vertices": V, "edges": n, "ms": round(ms, 3),
+                                       "Gedges_s": round(n / (ms / 1e3) / 1e9, 3),
+                                       "max_in_degree": int(indeg.max()), "paper_context": "TW (1.47e9 edges) 0.888 s, "
+                                       "SD (2.04e9) 1.10 s on 96 cores"}
+    del off, tgt, indeg
+    torch.cuda.empty_cache()
+    for dims in (2, 3):
+        log(f"morton {dims}-D: {n} points")
+        c = W.varden_points(n, dims, seed=0, device=dev).to(torch.int32)
+        ms = timed(lambda: dt.morton_sort(c, opts=o))
+        res[f"morton_{dims}d_varden"] = {"points": n, "ms": round(ms, 3), "Gpoints_s": round(n / (ms / 1e3) / 1e9, 3),
+                                         "paper_context": f"Varden SS{dims}d (1e9 points) "
+                                                          f"{0.498 if dims == 2 else 0.512} s on 96 cores"}
+        del c
+        torch.cuda.empty_cache()
+    print(json.dumps({"apps": "Section 6.2 applications on synthetic stand-ins", "n": n, "steps": steps,
+                      "results": res}), flush=True)
 
 
 def run_extra(dt, W, torch, np, n, args, opts):

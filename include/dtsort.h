@@ -260,6 +260,33 @@ int dtsort_mlp_train_u64(const uint64_t* sorted_keys, size_t n, uint64_t seed, i
 int dtsort_segmented_noalloc(uint32_t* keys, uint32_t* values, size_t n_total, const uint64_t* seg_offsets,
                              size_t n_segments, const dtsort_opts* opts, void* stream);
 
+/* ---- the paper's applications (Section 6.2) over the 32+32-bit sort ---- */
+
+/* Graph transpose: the directed graph with V = n_vertices vertices and
+ * E = n_edges edges in compressed sparse row form (offsets: V + 1 uint64,
+ * offsets[0] = 0, non-decreasing, offsets[V] = E; targets: E uint32 < V; the
+ * out-edges of u are targets[offsets[u] .. offsets[u+1])) is reversed: every
+ * edge (u, v) becomes (v, u).  The result, also in CSR form, goes to
+ * t_offsets (V + 1) and t_targets (E): the in-neighbours of v, in the order
+ * the edges were listed (sources ascending) -- a stable sort of the edges by
+ * target.  All arrays are device memory; the inputs are not modified.
+ * Temporary memory: E keys from the per-device cache, and the sort's own.
+ * Invalid offsets or targets return DTSORT_EINVAL (checked on the device; the
+ * call synchronises `stream` to read the check).  opts as for the sorts (no
+ * graph form, no LEARNED mode). */
+int dtsort_graph_transpose(const uint64_t* offsets, const uint32_t* targets, uint32_t n_vertices, size_t n_edges,
+                           uint64_t* t_offsets, uint32_t* t_targets, const dtsort_opts* opts, void* stream);
+
+/* Morton order of n points with dims = 2 or 3 coordinates (coords: dims * n
+ * uint32, coordinate j of point i at coords[j * n + i]; the low 32 / dims
+ * bits of each coordinate are used): codes[i] gets the z-value of point i
+ * (bit b of coordinate j at bit dims * b + j), then codes are sorted stably
+ * with perm (= point indices) as values.  On return codes holds the sorted
+ * z-values and perm the points in Morton order (equal z-values by index).
+ * Device memory; enqueued on `stream` like the sorts. */
+int dtsort_morton_u32(const uint32_t* coords, int dims, size_t n, uint32_t* codes, uint32_t* perm,
+                      const dtsort_opts* opts, void* stream);
+
 /* Plain copy of n 32-bit words from src to dst (device, not overlapping) with
  * the copy kernel the sorts use for finished buckets; enqueued on `stream`.
  * A measurement aid: the HBM rate this kernel reaches is the practical ceiling

@@ -13,7 +13,8 @@ from . import _lib
 from ._lib import (MERGE_GATHER, MERGE_INPLACE, MERGE_NONE, MERGE_PLMERGE, MERGE_SPLIT, MODE_LEARNED,  # noqa: F401
                    MODE_PLAIN, MODE_SAMPLING, DTSortError, Opts, Stats)
 
-__all__ = ["sort_u32", "sort_u64", "sort_pairs_u64", "sort_pairs_u32", "sort_segmented", "sort_segmented_noalloc", "copy_u32", "make_opts", "Stats",
+__all__ = ["sort_u32", "sort_u64", "sort_pairs_u64", "sort_pairs_u32", "sort_segmented", "sort_segmented_noalloc", "graph_transpose",
+           "morton_sort", "copy_u32", "make_opts", "Stats",
            "MODE_SAMPLING", "MODE_PLAIN", "MODE_LEARNED", "MERGE_GATHER", "MERGE_PLMERGE", "MERGE_INPLACE",
            "MERGE_NONE", "MERGE_SPLIT", "DTSortError"]
 
@@ -121,6 +122,40 @@ def sort_segmented_noalloc(keys, offsets, values=None, opts: Opts | None = None)
     _lib.check(_lib.load().dtsort_segmented_noalloc(keys.data_ptr(), vp, keys.numel(), offsets.data_ptr(),
                                                     offsets.numel() - 1, C.byref(o), _stream(keys)))
     return keys if values is None else (keys, values)
+
+
+def graph_transpose(offsets, targets, n_vertices: int, opts: Opts | None = None):
+    """Reverse every edge of a CSR graph (offsets: int64 [V + 1], targets:
+    int32 [E], device tensors); returns (t_offsets, t_targets) in CSR form,
+    in-neighbours in edge-list order."""
+    import torch
+    _check_tensor(offsets, 8)
+    _check_tensor(targets, 4)
+    if offsets.numel() != n_vertices + 1:
+        raise ValueError("offsets must hold n_vertices + 1 entries")
+    t_off = torch.empty_like(offsets)
+    t_tgt = torch.empty_like(targets)
+    o = opts if opts is not None else make_opts()
+    _lib.check(_lib.load().dtsort_graph_transpose(offsets.data_ptr(), targets.data_ptr(), n_vertices, targets.numel(),
+                                                  t_off.data_ptr(), t_tgt.data_ptr(), C.byref(o), _stream(targets)))
+    return t_off, t_tgt
+
+
+def morton_sort(coords, opts: Opts | None = None):
+    """Morton order of points coords [dims, n] (int32, dims 2 or 3, low
+    32 // dims bits per coordinate): returns (sorted z-values, point indices)."""
+    import torch
+    if coords.dim() != 2:
+        raise ValueError("coords must be [dims, n]")
+    c = coords.contiguous()
+    _check_tensor(c, 4)
+    dims, n = c.shape
+    codes = torch.empty(n, dtype=torch.int32, device=c.device)
+    perm = torch.empty(n, dtype=torch.int32, device=c.device)
+    o = opts if opts is not None else make_opts()
+    _lib.check(_lib.load().dtsort_morton_u32(c.data_ptr(), dims, n, codes.data_ptr(), perm.data_ptr(), C.byref(o),
+                                             _stream(c)))
+    return codes, perm
 
 
 def copy_u32(dst, src):

@@ -94,6 +94,8 @@ _SIGS = {
     "dtsort_mlp_loss_grad": (_I, [_P, _P, _P, _Z, _P, _P, _P]),
     "dtsort_mlp_forward": (_I, [_P, _P, _Z, _P, _P]),
     "dtsort_mlp_train_u64": (_I, [_P, _Z, C.c_uint64, _I, _I, C.c_float, _P, _P, _P]),
+    "dtsort_graph_transpose": (_I, [_P, _P, C.c_uint32, _Z, _P, _P, C.POINTER(Opts), _P]),
+    "dtsort_morton_u32": (_I, [_P, _I, _Z, _P, _P, C.POINTER(Opts), _P]),
     "dtsort_copy_u32": (_I, [_P, _P, _Z, _P]),
     "dtsort_release": (None, []),
     "dtsort_last_error": (C.c_char_p, []),

@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libdtsort.so")
 
-SOURCES = ["k_dist.hip", "k_plan.hip", "k_tree.hip", "k_mlp.hip", "driver.hip", "steps.hip"]
+SOURCES = ["k_dist.hip", "k_plan.hip", "k_tree.hip", "k_mlp.hip", "apps.hip", "driver.hip", "steps.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

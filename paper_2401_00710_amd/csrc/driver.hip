@@ -64,6 +64,8 @@ struct Ctx {
   Work w;
   DevBuf lrn;
   DevBuf copy_items;  // item list of dtsort_copy_u32
+  DevBuf app_keys;    // graph transpose: the edges' targets as sort keys; then an error word
+  uint32_t* h_app = nullptr;  // pinned: the applications' error word
   LevelCounters* h_ctr = nullptr;  // pinned
   void* h_stage = nullptr;         // pinned staging
   hipEvent_t done = nullptr;
@@ -132,6 +134,7 @@ struct Prof {
 enum ProfKind { PK_PLAN = 0, PK_HIST, PK_SCAN, PK_SCATTER, PK_CHILDREN, PK_LEAF, PK_COPY, PK_MERGE };
 
 static std::mutex g_mu;
+static std::mutex g_app_mu;  // the applications' buffers (each application call holds it throughout)
 static std::vector<Ctx*> g_ctx;
 
 // Grow-only device buffer; synchronises `s` first when it must reallocate,
@@ -1187,6 +1190,56 @@ int dtsort_segmented_noalloc(uint32_t* keys, uint32_t* values, size_t n_total, c
   return noalloc_entry<uint32_t, NoVal>(keys, (NoVal*)nullptr, n_total, seg_offsets, n_segments, opts, stream);
 }
 
+int dtsort_graph_transpose(const uint64_t* offsets, const uint32_t* targets, uint32_t n_vertices, size_t n_edges,
+                           uint64_t* t_offsets, uint32_t* t_targets, const dtsort_opts* opts, void* stream) {
+  g_err.clear();
+  if (!offsets || !t_offsets) return fail(DTSORT_EINVAL, "offsets is NULL");
+  if (n_edges > 0 && (!targets || !t_targets)) return fail(DTSORT_EINVAL, "targets is NULL");
+  if (n_edges >= (1ull << 32)) return fail(DTSORT_EINVAL, "n_edges must be below 2^32");
+  if (n_vertices == 0xFFFFFFFFu) return fail(DTSORT_EINVAL, "n_vertices must be below 2^32 - 1");
+  if (opts && (opts->graph || opts->mode == DTSORT_MODE_LEARNED))
+    return fail(DTSORT_EINVAL, "the transpose runs the eager sort (no graph form, no LEARNED mode)");
+  hipStream_t s = (hipStream_t)stream;
+  Ctx* c;
+  int r;
+  if ((r = get_ctx(&c))) return r;
+  std::lock_guard<std::mutex> lk(g_app_mu);
+  if (!c->h_app && hipHostMalloc((void**)&c->h_app, 64) != hipSuccess) {
+    (void)hipGetLastError();
+    c->h_app = nullptr;
+    return fail(DTSORT_ENOMEM, "pinned host allocation failed");
+  }
+  const size_t kb = (4 * n_edges + 255) & ~(size_t)255;
+  if ((r = ensure(c->app_keys, kb + 256, s))) return r;
+  uint32_t* keys = (uint32_t*)c->app_keys.p;
+  uint32_t* err = (uint32_t*)((char*)c->app_keys.p + kb);
+  launch_zero_counters((LevelCounters*)err, 1, s);  // clears the error word (and the rest of one counter block)
+  launch_transpose_prepare(offsets, targets, n_vertices, n_edges, keys, t_targets, err, s);
+  HIPCHK(hipGetLastError());
+  // the stable sort of the edges by target; values = sources
+  if ((r = sort_entry<uint32_t, uint32_t>(keys, t_targets, n_edges, nullptr, 0, opts, stream))) return r;
+  launch_transpose_offsets(keys, n_edges, n_vertices, t_offsets, s);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(c->h_app, err, 4, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (*c->h_app & 1u) return fail(DTSORT_EINVAL, "offsets are not a valid CSR offsets array");
+  if (*c->h_app & 2u) return fail(DTSORT_EINVAL, "a target is not below n_vertices");
+  return DTSORT_OK;
+}
+
+int dtsort_morton_u32(const uint32_t* coords, int dims, size_t n, uint32_t* codes, uint32_t* perm,
+                      const dtsort_opts* opts, void* stream) {
+  g_err.clear();
+  if (dims != 2 && dims != 3) return fail(DTSORT_EINVAL, "dims must be 2 or 3");
+  if (n >= (1ull << 32)) return fail(DTSORT_EINVAL, "n must be below 2^32");
+  if (n > 0 && (!coords || !codes || !perm)) return fail(DTSORT_EINVAL, "NULL pointer");
+  if (n == 0) return DTSORT_OK;
+  hipStream_t s = (hipStream_t)stream;
+  launch_morton(coords, dims, n, codes, perm, s);
+  HIPCHK(hipGetLastError());
+  return sort_entry<uint32_t, uint32_t>(codes, perm, n, nullptr, 0, opts, stream);
+}
+
 int dtsort_copy_u32(uint32_t* dst, const uint32_t* src, size_t n, void* stream) {
   g_err.clear();
   if (n == 0) return DTSORT_OK;
@@ -1217,6 +1270,8 @@ static void free_ctx(Ctx* c) {
   free_work(c->w);
   free_buf(c->lrn);
   free_buf(c->copy_items);
+  free_buf(c->app_keys);
+  if (c->h_app) (void)hipHostFree(c->h_app);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   for (GraphEntry* e : c->graphs) free_graph(e);
   c->graphs.clear();

@@ -133,6 +133,17 @@ void launch_merge(const Merge* m, const uint32_t* n_merges, uint32_t merge_cap, 
                   const uint2* munits, const uint32_t* n_munits, uint32_t munit_cap, uint32_t munit_grid,
                   uint8_t* tab, Bufs<K, V> b, int variant, hipStream_t s);
 
+// Applications (apps.hip).  Graph transpose: *err gets bit 1 for invalid
+// offsets, bit 2 for a target outside [0, V); keys = the targets, src = the
+// edges' sources.  t_off[v] = edges with a sorted key below v, v in [0, V].
+void launch_transpose_prepare(const uint64_t* off, const uint32_t* tgt, uint32_t n_vertices, uint64_t n_edges,
+                              uint32_t* keys, uint32_t* src, uint32_t* err, hipStream_t s);
+void launch_transpose_offsets(const uint32_t* keys, uint64_t n_edges, uint32_t n_vertices, uint64_t* t_off,
+                              hipStream_t s);
+// Morton order: z-values (2 or 3 coordinates, coordinate j of point i at
+// coords[j * n + i], low 32/dims bits of each) and point indices.
+void launch_morton(const uint32_t* coords, int dims, uint64_t n, uint32_t* codes, uint32_t* idx, hipStream_t s);
+
 // Learned partitioner (k_mlp.hip).
 int mlp_loss_grad(const float* p, const float* x, const float* y, uint32_t n, float* grad, float* loss, float* part,
                   hipStream_t s);

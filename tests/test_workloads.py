@@ -140,3 +140,27 @@ def test_paper_grid_chunks_deterministic(monkeypatch):
         monkeypatch.setattr(gen, "_CHUNK", 777)
         assert torch.equal(W.paper_keys(fam, prm, 5000, 64, seed=8), a)
         monkeypatch.undo()
+
+
+def test_power_law_graph_shape():
+    V, E = 1 << 12, 200_000
+    off, tgt = W.power_law_graph(V, E, seed=3)
+    assert off.numel() == V + 1 and int(off[0]) == 0 and int(off[-1]) == E
+    assert bool((off[1:] >= off[:-1]).all())
+    assert int(tgt.min()) >= 0 and int(tgt.max()) < V
+    indeg = torch.bincount(tgt, minlength=V)
+    # Zipf(1) over 4096 vertices: the top vertex takes about 1/H_4096 ~ 11 % of the edges
+    assert 0.09 < float(indeg.max()) / E < 0.14
+    outdeg = off[1:] - off[:-1]
+    assert int(outdeg.max()) > 20 * E // V  # skewed out-degrees too
+
+
+def test_varden_points_range_and_density():
+    p = W.varden_points(100_000, 2, seed=4)
+    assert p.shape == (2, 100_000)
+    assert int(p.min()) >= 0 and int(p.max()) < 1 << 16
+    q = W.varden_points(50_000, 3, seed=5)
+    assert int(q.max()) < 1 << 10
+    # varying density: some grid cells are far fuller than the average
+    cells = torch.bincount((p[0] >> 12) * 16 + (p[1] >> 12), minlength=256)
+    assert int(cells.max()) > 4 * 100_000 // 256 and int(cells.min()) < 100_000 // 256 // 2

@@ -306,6 +306,60 @@ def paper_keys(family: str, param: float, n: int, bits: int, seed: int = 0, devi
     raise KeyError(family)
 
 
+# ------------------------------------------------------- applications
+# Synthetic stand-ins for the inputs of the paper's applications (Section
+# 6.2; its real graphs and point sets are not available here).
+
+
+def power_law_graph(n_vertices: int, n_edges: int, s_out: float = 0.8, s_in: float = 1.0, seed: int = 0,
+                    device="cpu"):
+    """A directed graph in CSR form (offsets int64 [V + 1], targets int64
+    [E]) whose out- and in-degrees follow Zipf laws over the vertices (social
+    and web graphs: a few vertices with very many edges).  Edge sources are
+    Zipf(s_out) ranks and targets Zipf(s_in) ranks, each mapped to vertex ids
+    by its own multiplicative bijection of [0, V) (V a power of two)."""
+    if n_vertices & (n_vertices - 1):
+        raise ValueError("n_vertices must be a power of two")
+    mask = n_vertices - 1
+    counts = torch.zeros(n_vertices, dtype=torch.int64, device=device)
+    for c0 in range(0, n_edges, _CHUNK):
+        m = min(_CHUNK, n_edges - c0)
+        r = zipf_ranks(m, s_out, n_vertices, seed + c0, device, stream=50)
+        u = ((r - 1) * 0x9E3779B1) & mask
+        counts += torch.bincount(u, minlength=n_vertices)
+    offsets = torch.zeros(n_vertices + 1, dtype=torch.int64, device=device)
+    offsets[1:] = torch.cumsum(counts, 0)
+    targets = torch.empty(n_edges, dtype=torch.int64, device=device)
+    for c0 in range(0, n_edges, _CHUNK):
+        m = min(_CHUNK, n_edges - c0)
+        r = zipf_ranks(m, s_in, n_vertices, seed + 7 + c0, device, stream=51)
+        targets[c0:c0 + m] = ((r - 1) * 0x2545F491) & mask
+    return offsets, targets
+
+
+def varden_points(n: int, dims: int, seed: int = 0, device="cpu", clusters: int = 64) -> torch.Tensor:
+    """Points with varying density in [0, 2^(32 // dims))^dims, coords[d][i]
+    (int64): a uniform background (10 %) and Gaussian clusters whose
+    centres are uniform and whose spreads span four orders of magnitude
+    (a stand-in for the varying-density generator the paper uses)."""
+    side = 1 << (32 // dims)
+    out = torch.empty(dims, n, dtype=torch.int64, device=device)
+    cu = uniform01(seed, 60, clusters * dims, device).view(clusters, dims) * side
+    sig = side * torch.pow(10.0, -1.0 - 4.0 * uniform01(seed, 61, clusters, device))
+    for c0 in range(0, n, _CHUNK):
+        m = min(_CHUNK, n - c0)
+        pick = (_lsr(rand64(seed, 62, m, device, start=c0), 1) % clusters)
+        bg = uniform01(seed, 63, m, device, start=c0) < 0.1
+        for d in range(dims):
+            u1 = uniform01(seed, 64 + 2 * d, m, device, start=c0)
+            u2 = uniform01(seed, 65 + 2 * d, m, device, start=c0)
+            g = torch.sqrt(-2.0 * torch.log1p(-u1)) * torch.cos(2.0 * math.pi * u2)  # Box-Muller
+            x = cu[pick, d] + sig[pick] * g
+            x = torch.where(bg, u1 * side, x)
+            out[d, c0:c0 + m] = torch.clamp(torch.floor(x), 0, side - 1).to(torch.int64)
+    return out
+
+
 # ---------------------------------------------------------------- configs
 CONFIGS = {
     # name: (key dtype, has values, default n)

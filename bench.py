@@ -619,10 +619,13 @@ def run_extra(dt, W, torch, np, n, args, opts):
             sl = dt.Stats()
             one(name + "_learned", lambda: dt.sort_pairs_u64(kw, vw, opts(stats=sl, mode=dt.MODE_LEARNED)), k, kw,
                 v, vw)
-            res[name + "_learned"].update(learned_used=int(sl.learned_used),
+            res[name + "_learned"].update(learned_trained=int(sl.learned_trained), learned_used=int(sl.learned_used),
                                           balance_learned=round(sl.learned_balance, 3),
                                           balance_digit=round(sl.sampling_balance, 3),
-                                          training_ms=round(sl.learned_ms, 3), levels=int(sl.levels))
+                                          cost_learned=round(sl.learned_cost / n, 3),
+                                          cost_digit=round(sl.sampling_cost / n, 3),
+                                          cost_ideal=round(sl.ideal_cost / n, 3),
+                                          judge_ms=round(sl.learned_ms, 3), levels=int(sl.levels))
             res["bexp_learned_speedup_vs_sampling"] = round(res[name]["ms"] / res[name + "_learned"]["ms"], 3)
         del k, v, kw, vw
     # batched: 4096 instances in one call vs one call per instance
@@ -655,16 +658,21 @@ def run_extra(dt, W, torch, np, n, args, opts):
     mw = torch.empty_like(mk)
     st_s = dt.Stats()
     one("mixture_u64_1e9_sampling", lambda: dt.sort_u64(mw, opts(stats=st_s)), mk, mw)
-    st_l = dt.Stats()
-    one("mixture_u64_1e9_learned", lambda: dt.sort_u64(mw, opts(stats=st_l, mode=dt.MODE_LEARNED)), mk, mw)
-    res["mixture_u64_1e9_learned"].update(learned_used=int(st_l.learned_used),
-                                          balance_learned=round(st_l.learned_balance, 3),
-                                          balance_digit=round(st_l.sampling_balance, 3),
-                                          training_ms=round(st_l.learned_ms, 3),
-                                          levels=int(st_l.levels))
+    for tag, judge in (("", 0), ("_forced", 1)):
+        st_l = dt.Stats()
+        nm = "mixture_u64_1e9_learned" + tag
+        one(nm, lambda: dt.sort_u64(mw, opts(stats=st_l, mode=dt.MODE_LEARNED, learned_judge=judge)), mk, mw)
+        res[nm].update(judge="cost judge" if judge == 0 else "model's zones forced",
+                       learned_trained=int(st_l.learned_trained), learned_used=int(st_l.learned_used),
+                       balance_learned=round(st_l.learned_balance, 3), balance_digit=round(st_l.sampling_balance, 3),
+                       cost_learned=round(st_l.learned_cost / n, 3), cost_digit=round(st_l.sampling_cost / n, 3),
+                       cost_ideal=round(st_l.ideal_cost / n, 3), judge_ms=round(st_l.learned_ms, 3),
+                       levels=int(st_l.levels))
     res["mixture_u64_1e9_sampling"]["levels"] = int(st_s.levels)
     res["learned_speedup_vs_sampling"] = round(res["mixture_u64_1e9_sampling"]["ms"] /
                                                res["mixture_u64_1e9_learned"]["ms"], 3)
+    res["learned_forced_speedup_vs_sampling"] = round(res["mixture_u64_1e9_sampling"]["ms"] /
+                                                      res["mixture_u64_1e9_learned_forced"]["ms"], 3)
     # the paper's own multicore numbers, as context only (96-core Xeon, 8-byte pairs)
     res["paper_context_96core_xeon"] = {"unif_1e9_32bit_pairs_s": 0.500, "zipf1_32bit_pairs_s": 0.601,
                                         "exp1_64bit_pairs_s": 0.976, "bexp10_64bit_pairs_s": 3.30}

@@ -91,6 +91,17 @@ typedef struct dtsort_stats {
   uint64_t records_pair_merged; /* records of paired base cases (32-bit keys without values): each is leaf-sorted
                                    as part of one half (counted in records_leaf_sorted) and then written once
                                    more by the merge of the two halves */
+  /* LEARNED mode: the judge's predicted work below the root, in record passes
+   * (records x (1 + distribution levels still needed, log2(zone / cutoff) /
+   * digit bits), from a held-out sample):
+   * for the sampling step's digit zones, for the model's zones (0 if not trained),
+   * and for an ideal even split into the model's number of zones.  The model is
+   * trained only when sampling_cost > 1.25 x ideal_cost, and its zones are used
+   * only when learned_cost < 0.9 x sampling_cost (or always, learned_judge = 1). */
+  int32_t learned_trained;      /* 1 if the model was trained */
+  float learned_cost;
+  float sampling_cost;
+  float ideal_cost;
 } dtsort_stats;
 
 typedef struct dtsort_opts {
@@ -122,6 +133,9 @@ typedef struct dtsort_opts {
                              shape (levels, tasks, heavy keys) depends on the seed alone (Appendix A);
                              0 (default) = unordered ranks from LDS atomics, faster.  Equal keys cannot
                              be told apart, so the sorted output is the same either way. */
+  int32_t learned_judge;  /* LEARNED: 0 = the cost judge decides (train only when the sampling plan leaves
+                             clearly more work than an ideal split; use the model's zones only when they are
+                             predicted cheaper); 1 = always train and use the model's zones */
   int32_t merge_variant;  /* Step 4 (Section 3.4) implementation, for the paper's merge study (Section 6.3):
                              0 = the dovetail merge as one out-of-place gather (default);
                              1 = PLMerge-style: a general parallel merge (merge path) of the zone's light

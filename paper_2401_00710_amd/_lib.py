@@ -38,6 +38,10 @@ class Stats(C.Structure):
         ("kernel_bytes", C.c_double * 8),
         ("kernel_launches", C.c_uint32 * 8),
         ("records_pair_merged", C.c_uint64),
+        ("learned_trained", C.c_int32),
+        ("learned_cost", C.c_float),
+        ("sampling_cost", C.c_float),
+        ("ideal_cost", C.c_float),
     ]
 
     KINDS = ("plan", "hist", "scan", "scatter", "children", "leaf", "copy", "merge")
@@ -65,6 +69,7 @@ class Opts(C.Structure):
         ("tile_shape", C.c_int32),
         ("graph", C.c_int32),
         ("ordered_ranks", C.c_int32),
+        ("learned_judge", C.c_int32),
         ("merge_variant", C.c_int32),
         ("workspace", C.c_void_p),
         ("workspace_bytes", C.c_size_t),

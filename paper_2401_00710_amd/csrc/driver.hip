@@ -338,31 +338,33 @@ static void add_stats(dtsort_stats* st, const LevelCounters& h, bool level) {
   st->records_pair_merged += h.st_pair_records;
 }
 
-struct LearnedInfoH {
-  float bal_learned, bal_digit;
-  uint32_t use_learned;
-  uint32_t light_held;
-  float final_loss;
-  uint32_t pad;
-};
-
 constexpr uint32_t LEARN_SAMPLE = 1u << 16;  // training sample (sorted by the method itself)
 constexpr uint32_t LEARN_HELD = 1u << 14;    // held-out sample for the balance judge
 
 // Learned root plan (LEARNED mode, root task already planned by the sampling
-// step): draw and sort the training sample, train the CDF model, derive the
-// splitters, and let the judge keep whichever zones balance the held-out
-// sample better.  Everything stays on the device; `info` receives the decision.
-// Zones of a learned root: at most 2^8 (255 splitters).  Finer learned zones
-// cost more than they balance: on 10^9 keys of the 64-bit mixture, 2^9 zones
+// step).  A held-out sample is drawn and the judge first predicts the work
+// the digit plan leaves and what an ideal split into the model's zones
+// would leave; only when the digit plan is predicted clearly worse (more
+// than TRAIN_MARGIN x) is the model trained: the training sample is drawn
+// and sorted by the method itself, the CDF model trained, its splitters
+// derived, and the judge keeps the model's zones when their predicted work
+// is below USE_MARGIN x the digit plan's (or always with opts->learned_judge
+// = 1).  The decision is read back once (the eager schedule synchronises per
+// level anyway); everything else stays on the device.
+// Zones of a learned root: at most 2^8 (255 splitters), with 8-bit digits
+// below them unless the caller fixes the width.  Finer learned zones cost
+// more than they balance: on 10^9 keys of the 64-bit mixture, 2^9 zones
 // (with 9-bit digits below) took 51 ms against 41 ms for 2^8.
 constexpr int LEARN_GAMMA = 8;
+constexpr float TRAIN_MARGIN = 1.25f;
+constexpr float USE_MARGIN = 0.9f;
 static int learned_gamma(size_t n, int gover) {
   return std::min(plan_gamma((uint32_t)std::min<size_t>(n, 0xFFFFFFFFu), gover), LEARN_GAMMA);
 }
 
 template <typename K, typename V>
-static int learned_root(Ctx* c, SortJob<K, V>& J, LevelArgs& a, hipStream_t s, void* info) {
+static int learned_root(Ctx* c, SortJob<K, V>& J, LevelArgs& a, hipStream_t s, LearnedInfo* info,
+                        LearnedInfo* h_info) {
   const dtsort_opts& o = J.o;
   // 128 steps: on the 64-bit mixture and the bit-exponential pairs the zones
   // balance as well as after 256 (or better), at half the training time
@@ -397,8 +399,22 @@ static int learned_root(Ctx* c, SortJob<K, V>& J, LevelArgs& a, hipStream_t s, v
   float* part = (float*)(base + o_part);
   float* losses = (float*)(base + o_l);
   uint64_t* spl = (uint64_t*)(base + o_spl);
-  learned_kernels_draw<K>(J.bufs.k[0], J.n, o.seed, 0x4C52u, N, samp, s);
+  const uint32_t zones = 1u << learned_gamma(J.n, o.digit_bits);
+  JudgeParams jp;
+  jp.scale = (float)J.n / (float)HN;
+  jp.cutoff = (float)a.cutoff;
+  jp.g_digit = plan_gamma((uint32_t)std::min<size_t>(J.n, 0xFFFFFFFFu), a.g_override);
+  jp.g_learned = a.g_learned_child > 0 ? a.g_learned_child : LEARN_GAMMA;
+  jp.force = o.learned_judge == 1;
+  jp.train_margin = TRAIN_MARGIN;
+  jp.use_margin = USE_MARGIN;
   learned_kernels_draw<K>(J.bufs.k[0], J.n, o.seed, 0x4C48u, HN, held, s);
+  learned_kernels_judge<K>(a.tasks, a.tab, held, HN, nullptr, zones, jp, info, losses, 0, s);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(h_info, info, sizeof(LearnedInfo), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (!h_info->trained) return 0;  // the digit zones are kept; nothing to train
+  learned_kernels_draw<K>(J.bufs.k[0], J.n, o.seed, 0x4C52u, N, samp, s);
   HIPCHK(hipGetLastError());
   // the training sample is sorted by the method itself, on separate state
   if (!c->inner) {
@@ -419,9 +435,10 @@ static int learned_root(Ctx* c, SortJob<K, V>& J, LevelArgs& a, hipStream_t s, v
   mlp_data<K>(samp, N, J.key_bits, x, y, s);
   mlp_train(x, y, N, o.seed, steps, batch, lr, par, m, v, part, losses, s);
   mlp_forward(par, x, N, pred, s);
-  learned_kernels_split<K>(samp, pred, N, 1u << learned_gamma(J.n, a.g_override), mono, spl, s);
-  learned_kernels_judge<K>(a.tasks, a.tab, held, HN, spl, info, losses, steps, s);
+  learned_kernels_split<K>(samp, pred, N, zones, mono, spl, s);
+  learned_kernels_judge<K>(a.tasks, a.tab, held, HN, spl, zones, jp, info, losses, steps, s);
   HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(h_info, info, sizeof(LearnedInfo), hipMemcpyDeviceToHost, s));
   return 0;
 }
 
@@ -432,17 +449,19 @@ static int run_sort(Ctx* c, SortJob<K, V>& J, hipStream_t s, dtsort_stats* stats
   const dtsort_opts& o = J.o;
   const Params P = resolve_params(J);
   const bool learned = o.mode == DTSORT_MODE_LEARNED && !J.seg && n >= (1u << 20);
-  // a learned root takes 2^8 zones; unless the caller fixed the digit width,
-  // the levels below it take 8-bit digits too (their buckets are the learned
-  // zones' children: 10^9 keys of the 64-bit mixture sort in 41 ms with 8-bit
-  // digits below the root against 49 ms with the 9 bits tuned for sampling)
-  const int gover = (learned && o.digit_bits == 0) ? LEARN_GAMMA : P.gover;
+  // the root is planned by the sampling step at the usual width (the judge
+  // may keep it); a learned root takes 2^8 zones and, unless the caller fixed
+  // the digit width, its children 8-bit digits (10^9 keys of the 64-bit
+  // mixture sorted in 41 ms with 8-bit digits below a learned root against
+  // 49 ms with 9 bits)
+  const int gover = P.gover;
   const uint32_t cutoff = P.cutoff;
   Work& W = c->w;
   LevelArgs a;
   std::memset(&a, 0, sizeof(a));
   a.seed = o.seed;
   a.g_override = gover;
+  a.g_learned_child = o.digit_bits > 0 ? o.digit_bits : LEARN_GAMMA;
   a.cutoff = cutoff;
   for (int k = 0; k < LEAF_CLASSES; ++k) a.leaf_max[k] = leaf_cap<K, V>(k);
   a.leaf_max[LEAF_PAIR] = pair_max<K, V>(cutoff);
@@ -534,8 +553,7 @@ static int run_sort(Ctx* c, SortJob<K, V>& J, hipStream_t s, dtsort_stats* stats
       return 0;
     }
     if ((r = ensure(W.tasks[cur], sizeof(Task), s))) return r;
-    launch_root<K>((Task*)W.tasks[cur].p, dctr, n, J.key_bits,
-                   learned ? learned_gamma(n, gover) : plan_gamma((uint32_t)n, gover), s);
+    launch_root<K>((Task*)W.tasks[cur].p, dctr, n, J.key_bits, plan_gamma((uint32_t)n, gover), s);
     n_tasks = 1;
     total = n;
     max_size = (uint32_t)n;
@@ -545,7 +563,9 @@ static int run_sort(Ctx* c, SortJob<K, V>& J, hipStream_t s, dtsort_stats* stats
   int L = 0;
   for (; n_tasks > 0; ++L) {
     if (L >= MAX_LEVELS) return fail(DTSORT_EINTERNAL, "recursion deeper than expected");
-    const int gmax = (L == 0 && learned) ? learned_gamma(n, gover) : plan_gamma(max_size, gover);
+    // (levels below a learned root: its children's width a.g_learned_child is
+    // at most LEARN_GAMMA <= plan_gamma of any size, or the caller's width)
+    const int gmax = plan_gamma(max_size, gover);
     // chunk: a multiple of 8192 records aiming at ~2048 units per level (the
     // prep kernel derives the same value when it is left 0)
     uint64_t chunk = (total + 2047) / 2048;
@@ -596,7 +616,7 @@ static int run_sort(Ctx* c, SortJob<K, V>& J, hipStream_t s, dtsort_stats* stats
       HIPCHK(hipEventCreate(&le0));
       HIPCHK(hipEventCreate(&le1));
       HIPCHK(hipEventRecord(le0, s));
-      if ((r = learned_root<K, V>(c, J, a, s, d_info))) return r;
+      if ((r = learned_root<K, V>(c, J, a, s, (LearnedInfo*)d_info, (LearnedInfo*)c->h_stage))) return r;
       HIPCHK(hipEventRecord(le1, s));
     }
     const uint32_t max_chunks = (uint32_t)(max_size / chunk + 1);
@@ -618,14 +638,18 @@ static int run_sort(Ctx* c, SortJob<K, V>& J, hipStream_t s, dtsort_stats* stats
     const LevelCounters h = c->h_ctr[L + 1];
     if (h.error) return fail(DTSORT_EINTERNAL, "device capacity check failed (flags " + std::to_string(h.error) + ")");
     if (learn_here && stats) {
-      LearnedInfoH li;
-      HIPCHK(hipMemcpy(&li, d_info, sizeof(li), hipMemcpyDeviceToHost));
+      // read back by learned_root into the pinned staging area (the level's synchronisation covers it)
+      const LearnedInfo li = *(const LearnedInfo*)c->h_stage;
       float ms = 0;
       HIPCHK(hipEventElapsedTime(&ms, le0, le1));
       stats->learned_used = (int32_t)li.use_learned;
+      stats->learned_trained = (int32_t)li.trained;
       stats->learned_balance = li.bal_learned;
       stats->sampling_balance = li.bal_digit;
       stats->learned_final_loss = li.final_loss;
+      stats->learned_cost = li.cost_learned;
+      stats->sampling_cost = li.cost_digit;
+      stats->ideal_cost = li.cost_ideal;
       stats->learned_ms = ms;
     }
     if (le0) (void)hipEventDestroy(le0), le0 = nullptr;
@@ -992,6 +1016,7 @@ static int prepare_job(K* keys, V* vals, size_t n, const uint64_t* seg, size_t n
   if (o.digit_bits < 0 || o.digit_bits > GMAX) return fail(DTSORT_EINVAL, "digit_bits out of range");
   if (o.tile_shape < 0 || o.tile_shape > 6) return fail(DTSORT_EINVAL, "tile_shape out of range");
   if (o.merge_variant < MV_GATHER || o.merge_variant > MV_SPLIT) return fail(DTSORT_EINVAL, "unknown merge_variant");
+  if (o.learned_judge < 0 || o.learned_judge > 1) return fail(DTSORT_EINVAL, "unknown learned_judge");
   if (o.graph && (o.mode == DTSORT_MODE_LEARNED || o.profile))
     return fail(DTSORT_EINVAL, "graph mode does not combine with LEARNED mode or profiling");
   if (seg && n_seg >= (1ull << 31)) return fail(DTSORT_EINVAL, "too many segments");

@@ -480,50 +480,66 @@ __global__ __launch_bounds__(1024) void k_splitters(const K* sk, const float* pr
   }
 }
 
-struct LearnedInfo {
-  float bal_learned, bal_digit;
-  uint32_t use_learned;
-  uint32_t light_held;
-  float final_loss;
-  uint32_t pad;
-};
+// Predicted work below a root plan, in record passes: a zone of s records
+// costs s x (1 + the distribution levels it still needs), a zone above the
+// base-case cutoff needing log2(s / cutoff) / g levels of g-bit digits (each
+// level divides a subproblem by about 2^g; counted fractionally, so that
+// zones just either side of the cutoff cost about the same, as the sampled
+// sizes are only estimates).  counts are held-out light keys per zone,
+// scaled by `scale` records each.
+__device__ inline float zone_levels(float sz, float cutoff, int g) {
+  return sz > cutoff ? log2f(sz / cutoff) / (float)g : 0.f;
+}
 
-// Judge: bucket-balance error (largest zone / ideal) of the light held-out
-// keys under the digit plan already in the slot and under the splitters; the
-// model's zones are used only when strictly better.  Then, if used, rewrite
-// the task's light-id table for splitter zones (heavy keys are the sampling
-// detector's) and mark the task.
+__device__ inline float zones_cost(const uint32_t* counts, uint32_t zones, float scale, float cutoff, int g) {
+  float tot = 0.f;
+  for (uint32_t z = 0; z < zones; ++z) {
+    const float sz = (float)counts[z] * scale;
+    tot += sz * (1.f + zone_levels(sz, cutoff, g));
+  }
+  return tot;
+}
+
+// Judge of the learned partitioner.  On a held-out sample of the task's
+// keys (heavy keys excluded: both plans share the sampling detector's), it
+// predicts the work each root plan leaves (zones_cost) for the digit plan
+// already in the slot (the sampling step's; keys above its sampled range
+// form one more zone) and, when splitters are given, for the model's Z
+// zones.  Without splitters it only records the digit plan's cost and the
+// cost of an ideal Z-zone split, and whether training could pay
+// (digit > train_margin x ideal).  With splitters the model's zones are used
+// when their cost is below use_margin x the digit plan's (or always with
+// `force`); then the task's light-id table is rewritten for splitter zones
+// and the task marked.  Balance errors (largest zone / ideal) are recorded
+// too.  One workgroup.
 template <typename K>
-__global__ __launch_bounds__(1024) void k_judge_apply(Task* task, uint8_t* tab, const K* held, uint32_t nh_keys,
-                                                      const uint64_t* spl_in, LearnedInfo* info,
-                                                      const float* losses, int steps) {
-  __shared__ uint32_t cd[1 << GMAX], cl[1 << GMAX];
+__global__ __launch_bounds__(1024) void k_judge(Task* task, uint8_t* tab, const K* held, uint32_t nh_keys,
+                                                const uint64_t* spl_in, uint32_t Z, JudgeParams jp, LearnedInfo* info,
+                                                const float* losses, int steps) {
+  __shared__ uint32_t cd[(1 << GMAX) + 1], cl[1 << GMAX];
   __shared__ uint32_t hz[1 << (GMAX - 1)];
   __shared__ K H[1 << (GMAX - 1)];
   __shared__ K SPL[1 << GMAX];
   __shared__ uint32_t light_cnt;
   __shared__ int use;
   Task t = *task;
-  const int g = t.gamma;
-  const uint32_t Z = 1u << g;
-  const SlotLayout sl = slot_layout(g, true);
+  const bool full = spl_in != nullptr;
+  const SlotLayout sl = slot_layout(t.gamma, true);
   uint8_t* slot = tab + t.tab_off;
   uint32_t* gL = (uint32_t*)(slot + sl.light);
   const uint64_t* gH = (const uint64_t*)(slot + sl.heavy);
   uint64_t* gS = (uint64_t*)(slot + sl.spl);
-  for (uint32_t i = threadIdx.x; i < Z; i += 1024) {
-    cd[i] = 0;
-    cl[i] = 0;
-  }
+  const uint32_t zd = 1u << t.w;
+  for (uint32_t i = threadIdx.x; i <= zd; i += 1024) cd[i] = 0;
+  for (uint32_t i = threadIdx.x; i < Z; i += 1024) cl[i] = 0;
   for (uint32_t i = threadIdx.x; i < t.n_heavy; i += 1024) H[i] = (K)gH[i];
-  for (uint32_t i = threadIdx.x; i + 1 < Z; i += 1024) SPL[i] = (K)spl_in[i];
+  if (full)
+    for (uint32_t i = threadIdx.x; i + 1 < Z; i += 1024) SPL[i] = (K)spl_in[i];
   if (threadIdx.x == 0) light_cnt = 0;
   __syncthreads();
   const K mhi = mask_below<K>(t.hi);
-  const uint32_t zd = 1u << t.w;
   for (uint32_t i = threadIdx.x; i < nh_keys; i += 1024) {
     const K k = held[i];
-    // heavy keys are excluded from the balance
     uint32_t lo = 0, m = t.n_heavy;
     while (m > 0) {
       const uint32_t half = m >> 1;
@@ -537,36 +553,52 @@ __global__ __launch_bounds__(1024) void k_judge_apply(Task* task, uint8_t* tab, 
     if (lo < t.n_heavy && H[lo] == k) continue;
     atomicAdd(&light_cnt, 1u);
     const K low = k & mhi;
-    if (t.top >= t.hi || shr<K>(low, t.top) == 0) {
-      const uint32_t z = (uint32_t)(shr<K>(low, t.shift) & (K)(zd - 1u));
-      atomicAdd(&cd[z], 1u);
-    }
-    uint32_t a = 0, n2 = Z - 1;
-    while (n2 > 0) {
-      const uint32_t half = n2 >> 1;
-      if (SPL[a + half] <= k) {
-        a += half + 1;
-        n2 -= half + 1;
-      } else {
-        n2 = half;
+    if (t.top >= t.hi || shr<K>(low, t.top) == 0)
+      atomicAdd(&cd[(uint32_t)(shr<K>(low, t.shift) & (K)(zd - 1u))], 1u);
+    else
+      atomicAdd(&cd[zd], 1u);  // above the sampled range: the overflow bucket
+    if (full) {
+      uint32_t a = 0, n2 = Z - 1;
+      while (n2 > 0) {
+        const uint32_t half = n2 >> 1;
+        if (SPL[a + half] <= k) {
+          a += half + 1;
+          n2 -= half + 1;
+        } else {
+          n2 = half;
+        }
       }
+      atomicAdd(&cl[a], 1u);
     }
-    atomicAdd(&cl[a], 1u);
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    uint32_t md = 0, ml = 0;
-    for (uint32_t z = 0; z < zd; ++z) md = max(md, cd[z]);
-    for (uint32_t z = 0; z < Z; ++z) ml = max(ml, cl[z]);
     const float lc = (float)max(light_cnt, 1u);
-    const float bd = (float)md / (lc / (float)zd);
-    const float bl = (float)ml / (lc / (float)Z);
-    info->bal_digit = bd;
-    info->bal_learned = bl;
+    uint32_t md = 0;
+    for (uint32_t z = 0; z < zd; ++z) md = max(md, cd[z]);
+    info->bal_digit = (float)md / (lc / (float)zd);
     info->light_held = light_cnt;
-    info->final_loss = steps > 0 ? losses[steps - 1] : 0.0f;
-    use = bl < bd;
-    info->use_learned = use;
+    info->cost_digit = zones_cost(cd, zd + 1, jp.scale, jp.cutoff, jp.g_digit);
+    // ideal: the light keys spread evenly over Z zones
+    const float each = (float)light_cnt / (float)Z * jp.scale;
+    info->cost_ideal = (float)light_cnt * jp.scale * (1.f + zone_levels(each, jp.cutoff, jp.g_learned));
+    use = 0;
+    if (!full) {
+      info->trained = jp.force || info->cost_digit > jp.train_margin * info->cost_ideal;
+      info->use_learned = 0;
+      info->bal_learned = 0.f;
+      info->cost_learned = 0.f;
+      info->final_loss = 0.f;
+    } else {
+      uint32_t ml = 0;
+      for (uint32_t z = 0; z < Z; ++z) ml = max(ml, cl[z]);
+      info->bal_learned = (float)ml / (lc / (float)Z);
+      info->cost_learned = zones_cost(cl, Z, jp.scale, jp.cutoff, jp.g_learned);
+      info->trained = 1;
+      info->final_loss = steps > 0 ? losses[steps - 1] : 0.0f;
+      use = jp.force || info->cost_learned < jp.use_margin * info->cost_digit;
+      info->use_learned = use;
+    }
   }
   __syncthreads();
   if (!use) return;
@@ -602,7 +634,7 @@ __global__ __launch_bounds__(1024) void k_judge_apply(Task* task, uint8_t* tab, 
   }
   if (threadIdx.x == 0) {
     t.flags = (uint8_t)((t.flags & ~TF_SPLIT) | TF_LEARNED);
-    t.w = (uint8_t)g;
+    t.w = (uint8_t)(31 - __builtin_clz(Z));
     t.shift = 0;
     t.top = t.hi;
     t.n_buckets = (uint16_t)(Z + t.n_heavy + 1);
@@ -621,17 +653,16 @@ void learned_kernels_split(const K* sk, const float* pred, uint32_t n, uint32_t 
   hipLaunchKernelGGL(k_splitters<K>, dim3(1), dim3(1024), 0, s, sk, pred, n, zones, mono, spl);
 }
 template <typename K>
-void learned_kernels_judge(Task* task, uint8_t* tab, const K* held, uint32_t nh, const uint64_t* spl, void* info,
-                           const float* losses, int steps, hipStream_t s) {
-  hipLaunchKernelGGL(k_judge_apply<K>, dim3(1), dim3(1024), 0, s, task, tab, held, nh, spl, (LearnedInfo*)info,
-                     losses, steps);
+void learned_kernels_judge(Task* task, uint8_t* tab, const K* held, uint32_t nh, const uint64_t* spl, uint32_t zones,
+                           const JudgeParams& jp, LearnedInfo* info, const float* losses, int steps, hipStream_t s) {
+  hipLaunchKernelGGL(k_judge<K>, dim3(1), dim3(1024), 0, s, task, tab, held, nh, spl, zones, jp, info, losses, steps);
 }
 #define DTS_INST(K)                                                                                           \
   template void learned_kernels_draw<K>(const K*, uint64_t, uint64_t, uint32_t, uint32_t, K*, hipStream_t);   \
   template void learned_kernels_split<K>(const K*, const float*, uint32_t, uint32_t, float*, uint64_t*,      \
                                          hipStream_t);                                                       \
-  template void learned_kernels_judge<K>(Task*, uint8_t*, const K*, uint32_t, const uint64_t*, void*,        \
-                                         const float*, int, hipStream_t);
+  template void learned_kernels_judge<K>(Task*, uint8_t*, const K*, uint32_t, const uint64_t*, uint32_t,     \
+                                         const JudgeParams&, LearnedInfo*, const float*, int, hipStream_t);
 DTS_INST(uint32_t)
 DTS_INST(uint64_t)
 #undef DTS_INST

@@ -404,7 +404,8 @@ __global__ __launch_bounds__(256) void k_children(LevelArgs a) {
   __syncthreads();
 #pragma unroll
   for (int k = 0; k <= ZPT; ++k)
-    if (ch[k].kind >= 0) write_child(a, ch[k], r.base[ch[k].kind], t.n_root, t.level + 1, a.g_override);
+    if (ch[k].kind >= 0)
+      write_child(a, ch[k], r.base[ch[k].kind], t.n_root, t.level + 1, learned ? a.g_learned_child : a.g_override);
 #pragma unroll
   for (int k = 0; k < ZPT; ++k) {
     if (mslot[k] == 0xFFFFFFFFu) continue;

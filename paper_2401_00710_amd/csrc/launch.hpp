@@ -42,6 +42,7 @@ struct LevelArgs {
   int tile;  // scatter tile shape (0..4, see launch_distribute)
   int ordered;  // keys without values: keep equal-bucket keys in input order (stable ranks)
   int merge_variant;  // MergeVariant: how zones with heavy keys are merged
+  int g_learned_child;  // digit-width override of the children of a learned root
   uint32_t grid_tasks;  // launch grid of the per-task kernels
   uint32_t grid_units;  // launch grid of the per-unit kernels
 };
@@ -158,9 +159,28 @@ void learned_kernels_draw(const K* keys, uint64_t n, uint64_t seed, uint32_t tag
 template <typename K>
 void learned_kernels_split(const K* sk, const float* pred, uint32_t n, uint32_t zones, float* mono, uint64_t* spl,
                            hipStream_t s);
+// The learned partitioner's decision record (device, read back by the host).
+struct LearnedInfo {
+  float bal_learned, bal_digit;  // balance errors (largest zone / ideal) of the held-out light keys
+  uint32_t use_learned;          // 1: the model's zones replaced the digit zones
+  uint32_t light_held;           // held-out keys that are light
+  float final_loss;              // training loss of the last step
+  uint32_t trained;              // 1: the model was trained (the digit plan's cost left room for a gain)
+  float cost_digit, cost_learned, cost_ideal;  // predicted record passes below each root plan
+};
+struct JudgeParams {
+  float scale;         // records a held-out key stands for
+  float cutoff;        // base-case size
+  int g_digit;         // digit width below a digit-zone root
+  int g_learned;       // digit width below a learned root
+  int force;           // use the model's zones whatever the costs
+  float train_margin;  // train only if the digit plan's cost exceeds this x the ideal split's
+  float use_margin;    // use the model's zones only if their cost is below this x the digit plan's
+};
+// spl = nullptr: the pre-training check only (digit plan and ideal costs, `trained` = whether to train).
 template <typename K>
-void learned_kernels_judge(Task* task, uint8_t* tab, const K* held, uint32_t nh, const uint64_t* spl, void* info,
-                           const float* losses, int steps, hipStream_t s);
+void learned_kernels_judge(Task* task, uint8_t* tab, const K* held, uint32_t nh, const uint64_t* spl, uint32_t zones,
+                           const JudgeParams& jp, LearnedInfo* info, const float* losses, int steps, hipStream_t s);
 constexpr int MLP_PARAMS = 4353;
 constexpr int MLP_GT = 64;  // samples per gradient workgroup (partial-gradient buffer sizing)
 

@@ -148,23 +148,30 @@ def test_full_pairs_u64(kind, mode):
         assert np.all(vv[1:][eq] > vv[:-1][eq])
 
 
-@pytest.mark.parametrize("mode", ["learned", "sampling"])
+@pytest.mark.parametrize("mode", ["learned", "learned_forced", "sampling"])
 def test_full_mixture_u64(mode):
+    """learned: the cost judge decides (its decision must follow its own
+    predicted costs); learned_forced: the model's zones in use, so that the
+    learned root's levels run at full size."""
     require_gpu()
     say(f"full mixture u64, {mode}: generate")
     src = W.mixture_u64(N, seed=0, device="cuda")
     inp = _host(src, np.uint64)
     st = dt.Stats()
     say("  sort")
-    m = dt.MODE_LEARNED if mode == "learned" else dt.MODE_SAMPLING
-    dt.sort_u64(src, dt.make_opts(tuned=1, mode=m, stats=st))
+    m = dt.MODE_SAMPLING if mode == "sampling" else dt.MODE_LEARNED
+    dt.sort_u64(src, dt.make_opts(tuned=1, mode=m, stats=st, learned_judge=1 if mode == "learned_forced" else 0))
     torch.cuda.synchronize()
     out = _host(src, np.uint64)
     del src
     torch.cuda.empty_cache()
-    say(f"  learned_used={st.learned_used}")
-    if mode == "learned":
+    say(f"  learned_trained={st.learned_trained} used={st.learned_used} costs digit {st.sampling_cost:.3g} "
+        f"learned {st.learned_cost:.3g} ideal {st.ideal_cost:.3g}")
+    if mode == "learned_forced":
         assert st.learned_used == 1
+    if mode == "learned":
+        assert st.learned_trained == (st.sampling_cost > 1.25 * st.ideal_cost)
+        assert st.learned_used == (st.learned_trained == 1 and st.learned_cost < 0.9 * st.sampling_cost)
     _check_keys(inp, out, 2)
 
 

@@ -60,7 +60,7 @@ def test_pairs_u32_forms(params):
     for rep in range(2 if params.get("graph") else 1):
         st = _check(k, 32, **params)
     if params.get("mode") == dt.MODE_LEARNED:
-        assert st.learned_balance > 0
+        assert st.sampling_balance > 0  # the judge ran (it trains only where a gain is predicted)
 
 
 GRID = [(f, p) for f, ps in W.PAPER_GRID.items() for p in ps]

@@ -85,20 +85,54 @@ def test_training_trajectory_close_to_oracle():
 
 @pytest.mark.parametrize("garbage", [False, True])
 def test_learned_sort_bit_exact(garbage):
+    """The model's zones forced in (learned_judge = 1), from a trained and from
+    a ruined model: the output is the oracle's either way."""
     require_gpu()
     say(f"learned sort garbage={garbage}")
     k = W.mixture_u64(1 << 22, seed=5).numpy().view(np.uint64)
     d = dev_u64(k)
     st = dt.Stats()
     kw = dict(learned_steps=1, learned_lr=50.0) if garbage else {}
-    dt.sort_u64(d, dt.make_opts(mode=dt.MODE_LEARNED, stats=st, digit_bits=8, **kw))
+    dt.sort_u64(d, dt.make_opts(mode=dt.MODE_LEARNED, stats=st, digit_bits=8, learned_judge=1, **kw))
     torch.cuda.synchronize()
     assert np.array_equal(host_u64(d), np.sort(k))
+    assert st.learned_trained == 1 and st.learned_used == 1
     assert st.learned_balance > 0 and st.sampling_balance > 0
     if not garbage:
-        # on the mixture the model's zones beat the digit zones (the exponential
-        # component sits in digit zone 0)
-        assert st.learned_used == 1 and st.learned_balance < st.sampling_balance
+        # on the mixture the model's zones balance better than the digit zones
+        # (the exponential component sits in digit zone 0)
+        assert st.learned_balance < st.sampling_balance
+
+
+def test_cost_judge_decisions():
+    """The judge trains only where the digit zones leave clearly more work
+    than an ideal split, and uses the model's zones only where they are
+    predicted cheaper.  Bit-exponential keys (almost every key in digit zone
+    0): trained and used, with less predicted work and better balance than
+    the method without the model.  Uniform keys: nothing to gain, no
+    training.  Both outputs bit-exact."""
+    require_gpu()
+    n = 1 << 22
+    kb = W.bit_exponential_keys(n, 0.1, seed=8).numpy().view(np.uint64)
+    d = dev_u64(kb)
+    st = dt.Stats()
+    dt.sort_u64(d, dt.make_opts(mode=dt.MODE_LEARNED, stats=st))
+    torch.cuda.synchronize()
+    assert np.array_equal(host_u64(d), np.sort(kb))
+    say(f"bexp: costs digit {st.sampling_cost:.3g} learned {st.learned_cost:.3g} ideal {st.ideal_cost:.3g}")
+    assert st.learned_trained == 1 and st.learned_used == 1
+    assert st.sampling_cost > 1.25 * st.ideal_cost
+    assert st.learned_cost < 0.9 * st.sampling_cost
+    assert st.learned_balance < st.sampling_balance
+    ku = W.uniform_u64(n, seed=9).numpy().view(np.uint64)
+    d = dev_u64(ku)
+    st2 = dt.Stats()
+    dt.sort_u64(d, dt.make_opts(mode=dt.MODE_LEARNED, stats=st2))
+    torch.cuda.synchronize()
+    assert np.array_equal(host_u64(d), np.sort(ku))
+    say(f"uniform: costs digit {st2.sampling_cost:.3g} ideal {st2.ideal_cost:.3g}")
+    assert st2.learned_trained == 0 and st2.learned_used == 0
+    assert st2.sampling_cost <= 1.25 * st2.ideal_cost
 
 
 def test_learned_pairs_stable():

@@ -154,5 +154,6 @@ def test_split_with_learned_root():
     k = W.mixture_u64(1 << 21, seed=4).numpy().view(np.uint64)
     v = np.arange(k.size, dtype=np.uint64)
     ek, ev = S.stable_sort_pairs(k, v)
-    gk, gv, st = _run("pairs64", k, merge_variant=dt.MERGE_SPLIT, mode=dt.MODE_LEARNED)
+    gk, gv, st = _run("pairs64", k, merge_variant=dt.MERGE_SPLIT, mode=dt.MODE_LEARNED, learned_judge=1)
     assert np.array_equal(gk, ek) and np.array_equal(gv, ev)
+    assert st.learned_used == 1

@@ -380,7 +380,7 @@ struct PlanRegs {
   bool top_full;  // top >= key width (no overflow test)
   bool heavy;     // the task has heavy keys (else the light id of zone z is z)
   bool hashed;    // the heavy keys are in the workgroup's hash table (set by the kernel)
-  bool split;     // split layout (TF_SPLIT)
+  bool split;     // the split layout (TF_SPLIT)
 };
 
 template <typename K>
@@ -417,58 +417,23 @@ __device__ inline uint32_t heavy_slot(K key) {
   return (x * 0x9E3779B1u) >> (32 - HT_BITS);
 }
 
-// Index in HT's heavy-key array of a key equal to `key`, or -1.
-template <typename K>
-__device__ inline int heavy_index_hashed(K key, const K* H, const uint32_t* HT) {
-  uint32_t w = HT[heavy_slot<K>(key)];
-#pragma unroll
-  for (int j = 0; j < HT_WAYS; ++j) {
-    const uint32_t e = w & 0xFFu;
-    if (e == 0xFFu) break;
-    if (H[e] == key) return (int)e;
-    w >>= 8;
-  }
-  return -1;
-}
-
-// Bucket id in the split layout (dovetailing at distribution time, a variant
-// derived from Section 3.4): zone z with heavy keys h_1 < ... < h_m has the
-// buckets light_0, h_1, light_1, ..., h_m, light_m in key order, so that a
-// heavy bucket lands between the light keys below and above it and no merge
-// is needed.  With e = the index of the key in the (globally ascending)
-// heavy-key array, heavy keys take id z + 2e + 1 and a light key takes
-// z + 2 * (heavy keys below it); L[z] = z + 2 * (heavy keys of lower zones).
-template <typename K>
-__device__ inline uint32_t split_bucket(K key, uint32_t z, uint32_t lid, const PlanRegs<K>& p, const uint32_t* L,
-                                        const K* H, const uint32_t* HT) {
-  if (p.hashed) {
-    const int e = heavy_index_hashed<K>(key, H, HT);
-    if (e >= 0) return z + 2u * (uint32_t)e + 1u;
-  }
-  const uint32_t m = (L[z + 1] - lid - 1u) >> 1;
-  if (m == 0) return lid;
-  const uint32_t base = (lid - z) >> 1;
-  uint32_t lo = base, n = m;
-  while (n > 0) {
-    const uint32_t half = n >> 1;
-    if (H[lo + half] < key) {
-      lo += half + 1;
-      n -= half + 1;
-    } else {
-      n = half;
-    }
-  }
-  if (!p.hashed && lo < base + m && H[lo] == key) return z + 2u * lo + 1u;
-  return z + 2u * lo;
-}
-
 // Bucket id of `key`: overflow if a bit in [top, hi) is set (Section 5); else
 // the heavy id if the key is one of its zone's heavy keys; else the zone's
 // light id.  L (light ids, 2^w + 1 entries), H (heavy keys), SPL
 // (splitters, learned root) and HT (the heavy-key hash table, used when
 // p.hashed) are in LDS.  Without the table the heavy keys of the key's zone
 // are binary-searched.
-template <typename K>
+//
+// Split layout (p.split, dovetailing during distribution, a variant derived
+// from Section 3.4): zone z with heavy keys h_1 < ... < h_m has the buckets
+// light_0, h_1, light_1, ..., h_m, light_m in key order, so that a heavy
+// bucket lands between the light keys below and above it and no merge is
+// needed.  With the heavy keys' global ascending array H, a heavy key H[e]
+// takes id z + 2e + 1 and a light key z + 2 * (heavy keys below it), and
+// L[z] = z + 2 * (heavy keys of lower zones).  Only the SPLIT kernel
+// variants carry this path (so that the default ones carry none of its
+// code); there it serves the tasks marked split, by binary search.
+template <typename K, bool SPLIT = false>
 __device__ inline uint32_t bucket_of(K key, const PlanRegs<K>& p, const uint32_t* L, const K* H, const K* SPL,
                                      const uint32_t* HT) {
   K low = key & p.mask_hi;
@@ -492,7 +457,24 @@ __device__ inline uint32_t bucket_of(K key, const PlanRegs<K>& p, const uint32_t
   }
   if (!p.heavy) return z;
   uint32_t lid = L[z];
-  if (p.split) return split_bucket<K>(key, z, lid, p, L, H, HT);
+  if constexpr (SPLIT) {
+    if (p.split) {
+      const uint32_t m = (L[z + 1] - lid - 1u) >> 1;
+      const uint32_t base = (lid - z) >> 1;
+      uint32_t lo = base, n = m;
+      while (n > 0) {
+        const uint32_t half = n >> 1;
+        if (H[lo + half] < key) {
+          lo += half + 1;
+          n -= half + 1;
+        } else {
+          n = half;
+        }
+      }
+      if (lo < base + m && H[lo] == key) return z + 2u * lo + 1u;
+      return z + 2u * lo;
+    }
+  }
   if (p.hashed) {
     // an equal heavy key lies in this key's zone; its bucket follows the
     // zone's light bucket in the order of the heavy-key array

@@ -173,7 +173,8 @@ __device__ inline void load_tables(const Task& t, const uint8_t* tab, uint32_t* 
 // ------------------------------------------------------------- histogram
 // Units with a grid stride; the workgroup's counts of a unit go to its
 // column of the task's count matrix.
-template <typename K, int T, int ITEMS, int NBMAX>
+// SPLIT: tasks in the split bucket layout (bucket_of<K, true>).
+template <typename K, int T, int ITEMS, int NBMAX, bool SPLIT = false>
 __global__ __launch_bounds__(T) void k_hist(LevelArgs a, const K* k0, const K* k1) {
   constexpr int WAVES = T / WAVE;
   constexpr int GM = NBMAX <= NB8 ? 8 : (NBMAX <= NB9 ? 9 : GMAX);  // widest digit of this variant
@@ -202,7 +203,7 @@ __global__ __launch_bounds__(T) void k_hist(LevelArgs a, const K* k0, const K* k
     for (int i = threadIdx.x; i < WAVES * HC2 * NBMAX; i += T) hist[i] = 0;
     __syncthreads();
     PlanRegs<K> pr = plan_regs<K>(t);
-    pr.hashed = HASH && pr.heavy && hfull == 0u;
+    pr.hashed = HASH && pr.heavy && hfull == 0u && !(SPLIT && pr.split);
     const K* keys = (t.src ? k1 : k0) + t.off;
     const uint32_t beg = u.y * chunk;
     const uint32_t end = beg + min(chunk, t.size - beg);  // no wrap for sizes near 2^32
@@ -233,7 +234,7 @@ __global__ __launch_bounds__(T) void k_hist(LevelArgs a, const K* k0, const K* k
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
           const uint32_t e = i * T + threadIdx.x;  // place in the tile
-          bb[i] = (W || e < len) ? bucket_of<K>(kk[i], pr, L, H, SPL, HT) : 0u;
+          bb[i] = (W || e < len) ? bucket_of<K, SPLIT>(kk[i], pr, L, H, SPL, HT) : 0u;
         }
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
@@ -368,7 +369,7 @@ constexpr int scatter_min_waves() {
                                                               : 1;
 }
 
-template <typename K, typename V, int T, int ITEMS, int NBMAX, int RANK>
+template <typename K, typename V, int T, int ITEMS, int NBMAX, int RANK, bool SPLIT = false>
 __global__ __launch_bounds__(T, (scatter_min_waves<T, ITEMS, (int)(sizeof(K) * (HasVal<V>::value ? 2 : 1)), RANK>())) void k_scatter(
     LevelArgs a, Bufs<K, V> bf) {
   constexpr int WAVES = T / WAVE;
@@ -422,7 +423,7 @@ __global__ __launch_bounds__(T, (scatter_min_waves<T, ITEMS, (int)(sizeof(K) * (
     __syncthreads();
 
     PlanRegs<K> pr = plan_regs<K>(t);
-    pr.hashed = HASH && pr.heavy && hfull == 0u;
+    pr.hashed = HASH && pr.heavy && hfull == 0u && !(SPLIT && pr.split);
     const K* kin = bf.k[t.src] + t.off;
     K* kout = bf.k[1 - t.src] + t.off;
     const VT* vin = nullptr;
@@ -494,7 +495,7 @@ __global__ __launch_bounds__(T, (scatter_min_waves<T, ITEMS, (int)(sizeof(K) * (
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
           vl[i] = (uint32_t)striped_index<T, ITEMS>(i) < tile_n;
-          bk[i] = vl[i] ? bucket_of<K>(kk[i], pr, L, H, SPL, HT) : 0u;
+          bk[i] = vl[i] ? bucket_of<K, SPLIT>(kk[i], pr, L, H, SPL, HT) : 0u;
         }
         rank_pipelined<ITEMS>(bk, vl, wm, crow, pos);
       }
@@ -503,7 +504,7 @@ __global__ __launch_bounds__(T, (scatter_min_waves<T, ITEMS, (int)(sizeof(K) * (
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
           const uint32_t e = (uint32_t)striped_index<T, ITEMS>(i);
-          bk[i] = e < tile_n ? bucket_of<K>(kk[i], pr, L, H, SPL, HT) : 0u;
+          bk[i] = e < tile_n ? bucket_of<K, SPLIT>(kk[i], pr, L, H, SPL, HT) : 0u;
         }
       }
       if constexpr (ATOM) {
@@ -662,7 +663,7 @@ __global__ __launch_bounds__(T, (scatter_min_waves<T, ITEMS, (int)(sizeof(K) * (
   }
 }
 
-template <typename K, typename V, int NBMAX, int T, int RANK, int SITEMS_REQ = 0>
+template <typename K, typename V, int NBMAX, int T, int RANK, int SITEMS_REQ = 0, bool SPLIT = false>
 static void launch_dist_variant(const LevelArgs& a, Bufs<K, V> b, uint32_t max_chunks, hipStream_t s, int phase) {
   constexpr int HITEMS = sizeof(K) == 4 ? 16 : 8;
   constexpr int HT = T > 512 ? 512 : T;  // the histogram of 1024-thread tiles runs faster at 512
@@ -670,7 +671,7 @@ static void launch_dist_variant(const LevelArgs& a, Bufs<K, V> b, uint32_t max_c
   const uint32_t nu = a.grid_units;
   const uint32_t nt = a.grid_tasks;
   if (phase < 0 || phase == 0)
-    hipLaunchKernelGGL((k_hist<K, HT, HITEMS, NBMAX>), dim3(nu), dim3(HT), 0, s, a, (const K*)b.k[0],
+    hipLaunchKernelGGL((k_hist<K, HT, HITEMS, NBMAX, SPLIT>), dim3(nu), dim3(HT), 0, s, a, (const K*)b.k[0],
                        (const K*)b.k[1]);
   if (phase < 0 || phase == 1) {
     // bucket groups along y: all of them when the host knows the chunk
@@ -680,7 +681,7 @@ static void launch_dist_variant(const LevelArgs& a, Bufs<K, V> b, uint32_t max_c
     hipLaunchKernelGGL((k_bucketscan<NBMAX>), dim3(nt), dim3(256), 0, s, a);
   }
   if (phase < 0 || phase == 2)
-    hipLaunchKernelGGL((k_scatter<K, V, T, SITEMS, NBMAX, RANK>), dim3(nu), dim3(T), 0, s, a, b);
+    hipLaunchKernelGGL((k_scatter<K, V, T, SITEMS, NBMAX, RANK, SPLIT>), dim3(nu), dim3(T), 0, s, a, b);
 }
 
 uint32_t dist_cols(int) { return 1; }
@@ -719,6 +720,26 @@ void launch_distribute(const LevelArgs& a, Bufs<K, V> b, int g_level_max, uint32
     if (rm == RANK_ATOMIC) rm = RANK_LDS;
   } else if (!rank_mode_forced()) {
     rm = RANK_ATOMIC;
+  }
+  if (a.merge_variant == MV_SPLIT) {
+    // the split layout: one tile shape per digit class, LDS-match or atomic ranks
+    constexpr int UR = HasVal<V>::value ? RANK_LDS : RANK_ATOMIC;
+    const bool unordered = !HasVal<V>::value && !a.ordered;
+    if (g_level_max <= 8) {
+      if (unordered)
+        launch_dist_variant<K, V, NB8, 512, UR, 0, true>(a, b, max_chunks, s, phase);
+      else
+        launch_dist_variant<K, V, NB8, 512, RANK_LDS, 0, true>(a, b, max_chunks, s, phase);
+    } else if (g_level_max == 9 && unordered) {
+      if constexpr (!HasVal<V>::value)
+        launch_dist_variant<K, V, NB9, 1024, RANK_ATOMIC, sizeof(K) == 4 ? 16 : 8, true>(a, b, max_chunks, s, phase);
+    } else {
+      if (unordered)
+        launch_dist_variant<K, V, 2048, 256, UR, 0, true>(a, b, max_chunks, s, phase);
+      else
+        launch_dist_variant<K, V, 2048, 256, RANK_LDS, 0, true>(a, b, max_chunks, s, phase);
+    }
+    return;
   }
   if (g_level_max <= 8) {
     if (rm == RANK_BALLOT)

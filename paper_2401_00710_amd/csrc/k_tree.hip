@@ -256,7 +256,9 @@ void launch_seed_segments(const LevelArgs& a, const uint64_t* seg_off, uint32_t 
 
 // Child planning: one workgroup per task, one thread per zone (at most
 // 2^GMAX / 256 = 4 zones per thread, plus the overflow bucket on thread 0).
-template <typename K, typename V>
+// SPLITK: the variant for sorts with the split layout (MV_SPLIT), which adds
+// its bucket-by-bucket path; the default kernel carries none of its code.
+template <typename K, typename V, bool SPLITK>
 __global__ __launch_bounds__(256) void k_children(LevelArgs a) {
   constexpr int ZPT = (1 << GMAX) / 256;
   constexpr bool HV = HasVal<V>::value;
@@ -281,7 +283,7 @@ __global__ __launch_bounds__(256) void k_children(LevelArgs a) {
   // wrong buffer, the whole task range is copied as one item list instead of
   // bucket by bucket (the buckets are adjacent and in order).
   const bool whole_copy = !learned && t.shift == 0 && t.n_heavy == 0 && st[ob + 1] == st[ob] && dst != t.tgt;
-  if ((t.flags & TF_SPLIT) && t.n_heavy != 0 && !learned) {
+  if (SPLITK && (t.flags & TF_SPLIT) && t.n_heavy != 0 && !learned) {
     // Split layout: every light sub-bucket is a child with the task's target
     // (no merge follows); heavy buckets are finished where they landed.
     constexpr int SPT = (nb_cap(GMAX) + 255) / 256;  // buckets per thread
@@ -443,7 +445,10 @@ __global__ __launch_bounds__(256) void k_children(LevelArgs a) {
 template <typename K, typename V>
 void launch_children(const LevelArgs& a, Bufs<K, V> b, hipStream_t s) {
   (void)b;
-  hipLaunchKernelGGL((k_children<K, V>), dim3(a.grid_tasks), dim3(256), 0, s, a);
+  if (a.merge_variant == MV_SPLIT)
+    hipLaunchKernelGGL((k_children<K, V, true>), dim3(a.grid_tasks), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_children<K, V, false>), dim3(a.grid_tasks), dim3(256), 0, s, a);
 }
 
 // ------------------------------------------------------------------ copies

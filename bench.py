@@ -305,8 +305,9 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-ONCE = ("u32_1e9_uniform_and_zipf1", "uniform_u32_1e9", "zipf1_u32_1e9", "exp_pairs_u64_1e9", "bexp_pairs_u64_1e9", "uniform_u64_1e9",
-        "bexp_pairs_u64_1e9_learned", "mixture_u64_1e9", "mixture_u64_1e9_learned", "batched_4096_segments_graph",
+ONCE = ("u32_1e9_uniform_and_zipf1", "uniform_u32_1e9", "zipf1_u32_1e9", "exp_pairs_u64_1e9", "bexp_pairs_u64_1e9",
+        "bexp_pairs_u64_1e9_split", "uniform_u64_1e9", "bexp_pairs_u64_1e9_learned", "mixture_u64_1e9",
+        "mixture_u64_1e9_learned", "mixture_u64_1e9_learned_forced", "batched_4096_segments_graph",
         "batched_4096_segments")
 
 
@@ -339,8 +340,8 @@ def run_once(name, n):
         src = W.uniform_u64(n, seed=0, device=dev)
     elif name.startswith("mixture"):
         src = W.mixture_u64(n, seed=0, device=dev)
-        if name.endswith("learned"):
-            kw = dict(mode=dt.MODE_LEARNED)
+        if "learned" in name:
+            kw = dict(mode=dt.MODE_LEARNED, learned_judge=1 if name.endswith("forced") else 0)
     else:
         src = (W.exponential_keys(n, 1e-5, seed=0, device=dev) if name.startswith("exp")
                else W.bit_exponential_keys(n, 0.1, seed=0, device=dev))
@@ -348,6 +349,8 @@ def run_once(name, n):
         vals = torch.empty_like(vsrc)
         if name.endswith("learned"):
             kw = dict(mode=dt.MODE_LEARNED)
+        elif name.endswith("split"):
+            kw = dict(merge_variant=dt.MERGE_SPLIT)
     work = torch.empty_like(src)
     o = dt.make_opts(tuned=1, **kw)
     times = []

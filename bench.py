@@ -588,6 +588,12 @@ def run_extra(dt, W, torch, np, n, args, opts):
     m = statistics.median(ts)
     res["uniform_u32_2p20"] = dict(us=round(m * 1e3, 1), Gkeys_s=round(small.numel() / (m / 1e3) / 1e9, 3),
                                    protocol="6 runs, median of the last 5")
+    # the same in the graph form (the first call records; then one graph launch per sort, no host read-back)
+    og = opts(graph=1)
+    ts = timed_sorts(lambda: dt.sort_u32(sw, og), small, sw, 5, 1)
+    m = statistics.median(ts)
+    res["uniform_u32_2p20_graph"] = dict(us=round(m * 1e3, 1), Gkeys_s=round(small.numel() / (m / 1e3) / 1e9, 3),
+                                         protocol="6 runs, median of the last 5; the first records the graph")
     # n sweep of uniform u32 (where launch overhead stops mattering): prefixes of one 2^30 input
     big = W.uniform_u32(1 << 30, seed=0, device=dev).to(torch.int32)
     bw = torch.empty_like(big)

@@ -156,7 +156,8 @@ typedef struct dtsort_opts {
   dtsort_stats* stats;    /* optional host pointer */
 } dtsort_opts;
 
-/* Fill *opts with defaults (seed 0, automatic parameters, SAMPLING mode). */
+/* Fill *opts with defaults (seed 0, automatic parameters, SAMPLING mode;
+ * host memory, caller-owned; NULL is ignored). */
 void dtsort_default_opts(dtsort_opts* opts);
 
 /* Bytes of caller-supplied workspace needed for n records of key_bytes-wide
@@ -164,30 +165,45 @@ void dtsort_default_opts(dtsort_opts* opts);
  * the data (Section 5, "minimizing data movement"), rounded to 256 bytes. */
 size_t dtsort_workspace_bytes(int key_bytes, int val_bytes, size_t n);
 
-/* Stable ascending sort of n 32-bit keys in place. */
+/* Integer sort (Section 2.3) of n 32-bit keys in place: on return keys[0..n)
+ * holds the input keys in non-decreasing order (keys alone: the sorted
+ * multiset).  Method: Alg. 2 with Sections 3.1-3.5 and 5 (see the top of this
+ * file); opts->mode selects the heavy-key detection (Section 3.1), PLAIN the
+ * paper's ablation without it (Section 6.3).  keys: device, n elements,
+ * caller-owned.  opts may be NULL (defaults).  Errors: DTSORT_EINVAL for NULL
+ * keys with n > 0, n >= 2^32 or an option out of range (nothing written);
+ * DTSORT_ENOMEM, DTSORT_EHIP, DTSORT_EINTERNAL as above. */
 int dtsort_u32(uint32_t* keys, size_t n, const dtsort_opts* opts, void* stream);
 
-/* Stable ascending sort of n 64-bit keys in place. */
+/* The same for n 64-bit keys (Section 2.3; Section 6 sorts 64-bit keys too). */
 int dtsort_u64(uint64_t* keys, size_t n, const dtsort_opts* opts, void* stream);
 
-/* Stable sort of n (64-bit key, 64-bit value) records stored as two arrays
- * (structure of arrays); values move with their keys.  keys and values must
- * not overlap. */
+/* Stable integer sort (Section 2.3: records reordered by key, equal keys in
+ * their input order) of n (64-bit key, 64-bit value) records stored as two
+ * device arrays (structure of arrays, n elements each, caller-owned); values
+ * move with their keys.  The paper's 64-bit experiments sort such records
+ * (Section 6).  keys and values must not overlap (DTSORT_EINVAL otherwise,
+ * as for a NULL array with n > 0); other errors as for dtsort_u32. */
 int dtsort_pairs_u64(uint64_t* keys, uint64_t* values, size_t n, const dtsort_opts* opts, void* stream);
 
-/* Stable sort of n (32-bit key, 32-bit value) records stored as two arrays,
- * the record layout of the paper's 32-bit experiments (Section 6: 32-bit
- * keys with 32-bit values); values move with their keys.  keys and values
- * must not overlap. */
+/* Stable integer sort (Section 2.3) of n (32-bit key, 32-bit value) records
+ * stored as two device arrays, the record layout of the paper's 32-bit
+ * experiments and of both its applications (Section 6); values move with
+ * their keys.  keys and values must not overlap; errors as for
+ * dtsort_pairs_u64. */
 int dtsort_pairs_u32(uint32_t* keys, uint32_t* values, size_t n, const dtsort_opts* opts, void* stream);
 
-/* Batched form: n_segments independent stable sorts of 32-bit keys (and
- * optional 32-bit values, NULL for keys only) stored back to back.  Segment s
- * is [seg_offsets[s], seg_offsets[s+1]); seg_offsets is a DEVICE array of
+/* Batched form (not in the paper: many instances of Section 2.3's problem
+ * at once): n_segments independent stable sorts of 32-bit keys (and optional
+ * 32-bit values, NULL for keys only) stored back to back.  Segment s is
+ * [seg_offsets[s], seg_offsets[s+1]); seg_offsets is a DEVICE array of
  * n_segments + 1 uint64 with seg_offsets[0] = 0, non-decreasing and
  * seg_offsets[n_segments] = n_total (checked on the device; a violation
- * returns DTSORT_EINVAL).  Empty segments are allowed.  All segments are
- * processed level by level in shared launches. */
+ * returns DTSORT_EINVAL, found after the seeding step; with opts->graph = 1
+ * only when stats are requested).  Empty segments are allowed.  Every
+ * segment is a root subproblem of Alg. 2; all of them are processed level by
+ * level in shared launches.  keys/values: device, n_total elements,
+ * caller-owned; n_segments < 2^31. */
 int dtsort_segmented(uint32_t* keys, uint32_t* values, size_t n_total, const uint64_t* seg_offsets,
                      size_t n_segments, const dtsort_opts* opts, void* stream);
 
@@ -301,16 +317,19 @@ int dtsort_graph_transpose(const uint64_t* offsets, const uint32_t* targets, uin
 int dtsort_morton_u32(const uint32_t* coords, int dims, size_t n, uint32_t* codes, uint32_t* perm,
                       const dtsort_opts* opts, void* stream);
 
-/* Plain copy of n 32-bit words from src to dst (device, not overlapping) with
- * the copy kernel the sorts use for finished buckets; enqueued on `stream`.
- * A measurement aid: the HBM rate this kernel reaches is the practical ceiling
- * the sort's byte-moving kernels are compared with. */
+/* Plain copy of n 32-bit words from src to dst (device, caller-owned, not
+ * overlapping: DTSORT_EINVAL otherwise, and for NULL or n >= 2^32) with the
+ * copy kernel the sorts use for finished buckets (Section 5's buffer copies);
+ * enqueued on `stream`.  A measurement aid: the HBM rate this kernel reaches
+ * is the practical ceiling the sort's byte-moving kernels are compared with. */
 int dtsort_copy_u32(uint32_t* dst, const uint32_t* src, size_t n, void* stream);
 
-/* Release the per-device cache (call with no sort in flight). */
+/* Release the per-device cache of temporary buffers, graphs and streams
+ * (call with no sort in flight; the next call allocates again). */
 void dtsort_release(void);
 
-/* Message of the last error on the calling thread ("" if none). */
+/* Message of the last error on the calling thread ("" if none; the string
+ * is owned by the library and valid until the thread's next call). */
 const char* dtsort_last_error(void);
 const char* dtsort_strerror(int status);
 

@@ -808,9 +808,19 @@ static GPlan graph_plan(const SortJob<K, V>& J, const Params& P, int levels = 0)
   // sorters in a workgroup): about four times what fits at once, so that the
   // dispatcher hands the later workgroups to whichever CUs come free (leaves
   // differ in size; each workgroup takes a fixed stride of them)
+  // (a list of class k holds leaves of more than leaf_max[k-1] records, so at
+  // most n / (leaf_max[k-1] + 1) of them, which bounds small sorts' grids)
   const uint32_t per_cu[LEAF_CLASSES] = {64, 32, 16, 8, 8};
-  for (int k = 0; k < LEAF_CLASSES; ++k) g.grid_leaf[k] = pg(per_cu[k], c.leaf);
-  g.grid_pair = pair_leaves<K, V>() ? pg(1, c.leaf / 2 + 1) : 0;
+  for (int k = 0; k < LEAF_CLASSES; ++k) {
+    const uint64_t lo = k == 0 ? 1u : leaf_cap<K, V>(k - 1);
+    const uint64_t most = n / (lo + 1) + (J.seg ? J.n_seg + 1ull : 1ull);
+    g.grid_leaf[k] = pg(per_cu[k], std::min<uint64_t>(c.leaf, most));
+  }
+  // paired buckets hold more than the cutoff (two list entries each)
+  const uint64_t pairs_most = n / (g.cutoff + 1ull) + (J.seg ? J.n_seg + 1ull : 1ull);
+  if (pair_leaves<K, V>())
+    g.grid_leaf[LEAF_CLASSES - 1] = std::max(g.grid_leaf[LEAF_CLASSES - 1], pg(8, 2 * pairs_most));
+  g.grid_pair = pair_leaves<K, V>() ? pg(1, std::min<uint64_t>(c.leaf / 2 + 1, pairs_most)) : 0;
   g.grid_copy = pg(4, c.copies);
   g.grid_mpos = pg(32, c.merges);
   g.grid_munit = pg(16, c.munits);
@@ -1076,7 +1086,10 @@ static int graph_sort(Ctx* c, SortJob<K, V>& J, void* user_ws, hipStream_t s, dt
     for (size_t i = 0; i < sizeof(fk.ev) / sizeof(fk.ev[0]); ++i) fk.ev[i] = c->fork_events[i];
     hipError_t ce = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (ce == hipSuccess) {
-      graph_enqueue<K, V>(e->w, g, J2, P, cs, &fk);
+      // the second stream pays off where the segments sorted at seeding
+      // overlap level 0; a single sort's levels gain nothing from it, and
+      // every fork and join is a cross-stream wait in the graph
+      graph_enqueue<K, V>(e->w, g, J2, P, cs, J.seg ? &fk : nullptr);
       const hipError_t le = hipGetLastError();
       ce = hipStreamEndCapture(cs, &e->g);
       if (ce == hipSuccess) ce = le;

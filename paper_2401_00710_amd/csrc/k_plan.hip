@@ -186,7 +186,11 @@ void launch_plan(const LevelArgs& a, const K* k0, const K* k1, int g_level_max, 
   // largest sample of the level: 2^g * min(32, SCAP / 2^g) keys
   const uint32_t g = (uint32_t)g_level_max;
   const uint32_t ns = std::min<uint32_t>(32u, plan_sample_cap<K>() >> g) << g;
-  if (ns <= 512u * 16u) {
+  if (ns <= 1024u * 8u && a.grid_tasks <= 64u) {
+    // few subproblems (the root, small sorts): each sample sorted by twice the
+    // threads, so the level's critical path is shorter
+    hipLaunchKernelGGL((k_plan<K, 1024, 8>), dim3(a.grid_tasks), dim3(1024), 0, s, a, k0, k1);
+  } else if (ns <= 512u * 16u) {
     hipLaunchKernelGGL((k_plan<K, 512, 16>), dim3(a.grid_tasks), dim3(512), 0, s, a, k0, k1);
   } else {
     constexpr int IT = sizeof(K) == 4 ? 32 : 16;
@@ -221,10 +225,11 @@ __global__ __launch_bounds__(T* SUB) void k_leaf(const Leaf* items, const uint32
   uint32_t* cnt = cnt_all[sub];
   unsigned long long* mk = mk_all[sub];
   K* red = red_all[sub];
+  const uint32_t n_items = min(*count, cap);
+  if (blockIdx.x * SUB >= n_items) return;  // no leaf for this workgroup (persistent grids of sparse classes)
   if constexpr (USE_LDS) {
     for (int i = btid<T>(); i < bsort_match_words<T>(); i += T) mk[i] = 0ull;
   }
-  const uint32_t n_items = min(*count, cap);
   for (uint32_t li = blockIdx.x * SUB + sub; li < n_items; li += gridDim.x * SUB) {
     const Leaf it = items[li];
     const K* kin = bf.k[it.from] + it.off;

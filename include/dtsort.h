@@ -26,11 +26,14 @@
  *    last level's leaf sorts and the dovetail merges are left enqueued, so the
  *    caller synchronises `stream` before reading the result.
  *  - Temporary device memory (a ping-pong partner of the data plus small
- *    per-level tables) is taken from a per-device cache that grows as needed
- *    and is kept until dtsort_release() or process exit; or, for the large
- *    partner buffer, from opts->workspace when the caller supplies one.
- *    Calls on one device are serialised (each call waits for the previous
- *    call's work before reusing the cache).
+ *    per-level tables) is taken from a cache per (device, stream) that grows
+ *    as needed and is kept until dtsort_release() or process exit; or, for
+ *    the large partner buffer, from opts->workspace when the caller supplies
+ *    one.  Calls on different streams (from different host threads, say) run
+ *    concurrently, each with its own cache; calls on one stream are taken one
+ *    at a time.  Up to 8 streams per device keep a cache; a further stream
+ *    takes over the least recently used one (its calls then also wait for
+ *    that cache's previous work).
  *  - Return value: DTSORT_OK or a negative dtsort_status.  No exception ever
  *    crosses this interface.  On error nothing is guaranteed about the data
  *    except that no memory outside the given arrays is written.
@@ -300,7 +303,7 @@ int dtsort_segmented_noalloc(uint32_t* keys, uint32_t* values, size_t n_total, c
  * t_offsets (V + 1) and t_targets (E): the in-neighbours of v, in the order
  * the edges were listed (sources ascending) -- a stable sort of the edges by
  * target.  All arrays are device memory; the inputs are not modified.
- * Temporary memory: E keys from the per-device cache, and the sort's own.
+ * Temporary memory: E keys from the stream's cache, and the sort's own.
  * Invalid offsets or targets return DTSORT_EINVAL (checked on the device; the
  * call synchronises `stream` to read the check).  opts as for the sorts (no
  * graph form, no LEARNED mode). */
@@ -324,8 +327,9 @@ int dtsort_morton_u32(const uint32_t* coords, int dims, size_t n, uint32_t* code
  * is the practical ceiling the sort's byte-moving kernels are compared with. */
 int dtsort_copy_u32(uint32_t* dst, const uint32_t* src, size_t n, void* stream);
 
-/* Release the per-device cache of temporary buffers, graphs and streams
- * (call with no sort in flight; the next call allocates again). */
+/* Release every cache of temporary buffers, graphs and streams, of all
+ * devices and streams (call with no sort in flight; the next call allocates
+ * again). */
 void dtsort_release(void);
 
 /* Message of the last error on the calling thread ("" if none; the string

@@ -61,6 +61,10 @@ struct GraphEntry;
 
 struct Ctx {
   int device = -1;
+  hipStream_t owner = nullptr;  // the stream this context serves
+  std::mutex mu;                // one call at a time on this context
+  std::mutex app_mu;            // the applications' buffers (an application call holds it throughout)
+  uint64_t used = 0;            // registry tick of the last call (least recently used is taken over)
   Work w;
   DevBuf lrn;
   DevBuf copy_items;  // item list of dtsort_copy_u32
@@ -137,9 +141,14 @@ struct Prof {
 };
 enum ProfKind { PK_PLAN = 0, PK_HIST, PK_SCAN, PK_SCATTER, PK_CHILDREN, PK_LEAF, PK_COPY, PK_MERGE };
 
+// Contexts per device, one per stream: a call locks only its stream's
+// context, so calls on different streams run concurrently (each context has
+// its own buffers; a stream without a caller workspace gets its own partner
+// buffer).  g_mu guards the registry itself.
 static std::mutex g_mu;
-static std::mutex g_app_mu;  // the applications' buffers (each application call holds it throughout)
-static std::vector<Ctx*> g_ctx;
+static std::vector<std::vector<Ctx*>> g_ctx;
+static uint64_t g_tick = 0;
+constexpr size_t MAX_CTX_PER_DEVICE = 8;
 
 // Grow-only device buffer; synchronises `s` (and `s2`, when given) first
 // when it must reallocate, since earlier enqueued work may still use the old
@@ -181,17 +190,30 @@ static Ctx* new_ctx(int dev) {
   return c;
 }
 
-static int get_ctx(Ctx** out) {
+// The context of (current device, stream s).  Beyond MAX_CTX_PER_DEVICE
+// streams the least recently used context is taken over: its lock orders the
+// host calls, and a call on a stream other than the context's previous one
+// first waits for that stream's last work (sort_entry).
+static int get_ctx(hipStream_t s, Ctx** out) {
   int dev = 0;
   HIPCHK(hipGetDevice(&dev));
   std::lock_guard<std::mutex> lk(g_mu);
-  if ((int)g_ctx.size() <= dev) g_ctx.resize(dev + 1, nullptr);
-  if (!g_ctx[dev]) {
-    Ctx* c = new_ctx(dev);
-    if (!c) return fail(DTSORT_ENOMEM, "pinned host allocation failed");
-    g_ctx[dev] = c;
+  if ((int)g_ctx.size() <= dev) g_ctx.resize(dev + 1);
+  std::vector<Ctx*>& v = g_ctx[dev];
+  Ctx* hit = nullptr;
+  for (Ctx* c : v)
+    if (c->owner == s) hit = c;
+  if (!hit && v.size() < MAX_CTX_PER_DEVICE) {
+    hit = new_ctx(dev);
+    if (!hit) return fail(DTSORT_ENOMEM, "pinned host allocation failed");
+    hit->owner = s;
+    v.push_back(hit);
+  } else if (!hit) {
+    hit = *std::min_element(v.begin(), v.end(), [](const Ctx* a, const Ctx* b) { return a->used < b->used; });
+    hit->owner = s;
   }
-  *out = g_ctx[dev];
+  hit->used = ++g_tick;
+  *out = hit;
   return 0;
 }
 
@@ -1035,8 +1057,8 @@ static int graph_sort(Ctx* c, SortJob<K, V>& J, void* user_ws, hipStream_t s, dt
     if (c->graphs.size() >= MAX_GRAPHS) {
       auto it = std::min_element(c->graphs.begin(), c->graphs.end(),
                                  [](const GraphEntry* p, const GraphEntry* q) { return p->used < q->used; });
+      // every earlier call on this context is ordered before `s` (sort_entry)
       HIPCHK(hipStreamSynchronize(s));
-      HIPCHK(hipDeviceSynchronize());
       free_graph(*it);
       c->graphs.erase(it);
     }
@@ -1190,8 +1212,8 @@ static int sort_entry(K* keys, V* vals, size_t n, const uint64_t* seg, size_t n_
   const dtsort_opts& o = J.o;
   hipStream_t s = (hipStream_t)stream;
   Ctx* c;
-  if ((r = get_ctx(&c))) return r;
-  std::lock_guard<std::mutex> lk(g_mu);
+  if ((r = get_ctx(s, &c))) return r;
+  std::lock_guard<std::mutex> lk(c->mu);
   if (c->has_last && c->last_stream != s) HIPCHK(hipStreamWaitEvent(s, c->done, 0));
   // ping-pong partner
   const size_t need = dtsort_workspace_bytes((int)sizeof(K), HV ? (int)sizeof(V) : 0, n);
@@ -1363,8 +1385,8 @@ int dtsort_graph_transpose(const uint64_t* offsets, const uint32_t* targets, uin
   hipStream_t s = (hipStream_t)stream;
   Ctx* c;
   int r;
-  if ((r = get_ctx(&c))) return r;
-  std::lock_guard<std::mutex> lk(g_app_mu);
+  if ((r = get_ctx(s, &c))) return r;
+  std::lock_guard<std::mutex> lk(c->app_mu);
   if (!c->h_app && hipHostMalloc((void**)&c->h_app, 64) != hipSuccess) {
     (void)hipGetLastError();
     c->h_app = nullptr;
@@ -1411,8 +1433,8 @@ int dtsort_copy_u32(uint32_t* dst, const uint32_t* src, size_t n, void* stream) 
   hipStream_t s = (hipStream_t)stream;
   Ctx* c;
   int r;
-  if ((r = get_ctx(&c))) return r;
-  std::lock_guard<std::mutex> lk(g_mu);
+  if ((r = get_ctx(s, &c))) return r;
+  std::lock_guard<std::mutex> lk(c->mu);
   // items written on the device, cut as the sorts cut their copies
   const uint32_t items = pieces_of((uint32_t)n);
   if ((r = ensure(c->copy_items, sizeof(Leaf) * (size_t)items + 64, s))) return r;
@@ -1452,11 +1474,16 @@ static void free_ctx(Ctx* c) {
 
 void dtsort_release(void) {
   std::lock_guard<std::mutex> lk(g_mu);
-  for (Ctx* c : g_ctx) {
-    if (!c) continue;
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  for (size_t d = 0; d < g_ctx.size(); ++d) {
+    if (g_ctx[d].empty()) continue;
+    (void)hipSetDevice((int)d);
     (void)hipDeviceSynchronize();
-    free_ctx(c);
+    for (Ctx* c : g_ctx[d]) free_ctx(c);
   }
+  (void)hipSetDevice(cur);
+  (void)hipGetLastError();
   g_ctx.clear();
 }
 

@@ -154,6 +154,9 @@ typedef struct dtsort_opts {
                                  most subsample slots), so heavy buckets land in their final places and
                                  no merge is needed (a learned root's zones still merge as in 0).
                              Variants 0-2 and 4 give the same sorted output. */
+  int32_t digit_bits_below; /* digit width of the subproblems below the roots (every level after the first):
+                               0 = as digit_bits (with tuned = 1 and digit_bits 0: the tuning table's
+                               choice); else 1..10 */
   void* workspace;        /* optional device buffer for the ping-pong partner (see dtsort_workspace_bytes) */
   size_t workspace_bytes;
   dtsort_stats* stats;    /* optional host pointer */

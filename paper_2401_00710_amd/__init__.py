@@ -22,14 +22,14 @@ __all__ = ["sort_u32", "sort_u64", "sort_pairs_u64", "sort_pairs_u32", "sort_seg
 def make_opts(seed=0, key_bits=0, mode=MODE_SAMPLING, digit_bits=0, lds_cutoff=0, tuned=0,
               learned_steps=0, learned_batch=0, learned_lr=0.0, stats: Stats | None = None,
               workspace=None, profile=0, tile_shape=0, graph=0, ordered_ranks=0, merge_variant=0,
-              learned_judge=0) -> Opts:
+              learned_judge=0, digit_bits_below=0) -> Opts:
     o = Opts()
     _lib.load().dtsort_default_opts(C.byref(o))
     o.seed, o.key_bits, o.mode, o.digit_bits, o.lds_cutoff, o.tuned = seed, key_bits, mode, digit_bits, lds_cutoff, tuned
     o.learned_steps, o.learned_batch, o.learned_lr = learned_steps, learned_batch, learned_lr
     o.profile = profile
     o.tile_shape, o.graph, o.ordered_ranks, o.merge_variant = tile_shape, graph, ordered_ranks, merge_variant
-    o.learned_judge = learned_judge
+    o.learned_judge, o.digit_bits_below = learned_judge, digit_bits_below
     if stats is not None:
         o.stats = C.pointer(stats)
     if workspace is not None:

@@ -71,6 +71,7 @@ class Opts(C.Structure):
         ("ordered_ranks", C.c_int32),
         ("learned_judge", C.c_int32),
         ("merge_variant", C.c_int32),
+        ("digit_bits_below", C.c_int32),
         ("workspace", C.c_void_p),
         ("workspace_bytes", C.c_size_t),
         ("stats", C.POINTER(Stats)),

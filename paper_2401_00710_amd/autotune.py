@@ -5,10 +5,11 @@ For every record layout (32-bit keys, 64-bit keys, 64-bit pairs, the batched
 through the C ABI (the score of a parameter set is the summed time of the two
 input distributions the layout is benchmarked on, at the class size) and
 picks, by coordinate descent, the scatter tile shape, then the digit width,
-then the base-case cutoff.  The winners are written as rows of the text table
-the library reads when dtsort_opts.tuned = 1:
+then the digit width of the levels below the root, then the base-case
+cutoff.  The winners are written as rows of the text table the library reads
+when dtsort_opts.tuned = 1:
 
-    key_bytes val_bytes segmented log2n_lo log2n_hi digit_bits lds_cutoff tile_shape
+    key_bytes val_bytes segmented log2n_lo log2n_hi digit_bits lds_cutoff tile_shape digit_bits_below
 
 Usage (on a GPU):  python -m paper_2401_00710_amd.autotune --out tune_table.txt
 The output is only a speed choice: every parameter set sorts identically.
@@ -27,6 +28,7 @@ sys.path.insert(0, os.path.dirname(HERE))
 
 TILES = (1, 2, 3, 4, 5, 6)
 DIGITS = (8, 9, 10)
+DIGITS_BELOW = (8, 9)  # 0 (the start) = as digit_bits
 MIN_GAIN = 0.01  # a candidate replaces the current best only when it is at least this much faster
 
 
@@ -129,7 +131,8 @@ def tune(sizes, reps, log, cases=None):
             best["graph"] = 1
         t_best = score(best)
         tried = {json.dumps(best, sort_keys=True): t_best}
-        for key, values in (("tile_shape", TILES), ("digit_bits", DIGITS), ("lds_cutoff", _cutoffs(kb, vb))):
+        for key, values in (("tile_shape", TILES), ("digit_bits", DIGITS), ("digit_bits_below", DIGITS_BELOW),
+                            ("lds_cutoff", _cutoffs(kb, vb))):
             for v in values:
                 p = dict(best)
                 p[key] = v
@@ -142,7 +145,8 @@ def tune(sizes, reps, log, cases=None):
                 if t < t_best * (1.0 - MIN_GAIN):  # ties within timing noise keep the earlier choice
                     best, t_best = p, t
         log(f"{case} log2n [{lo},{hi}] best {best} {t_best:.3f} ms")
-        rows.append((kb, vb, seg, lo, hi, best["digit_bits"], best["lds_cutoff"], best["tile_shape"]))
+        rows.append((kb, vb, seg, lo, hi, best["digit_bits"], best["lds_cutoff"], best["tile_shape"],
+                     best.get("digit_bits_below", 0)))
         report.append(dict(case=case, n=int(work.numel()), best=best, ms=t_best,
                            tried={k: round(v, 4) for k, v in tried.items()}))
         del inps, work, vwork
@@ -157,7 +161,8 @@ def read_table(path):
         for line in open(path):
             if line.startswith("#") or not line.strip():
                 continue
-            rows.append(tuple(int(x) for x in line.split()))
+            r = tuple(int(x) for x in line.split())
+            rows.append(r + (0,) * (9 - len(r)))  # tables written before the last column: 0 there
     return rows
 
 
@@ -171,7 +176,8 @@ def merge_rows(old, new):
 def write_table(rows, path, device_name):
     with open(path, "w") as f:
         f.write("# Tuning table of libdtsort (read when dtsort_opts.tuned = 1).\n")
-        f.write("# Columns: key_bytes val_bytes segmented log2n_lo log2n_hi digit_bits lds_cutoff tile_shape\n")
+        f.write("# Columns: key_bytes val_bytes segmented log2n_lo log2n_hi digit_bits lds_cutoff tile_shape "
+                "digit_bits_below\n")
         f.write("# (0 = automatic).  First matching row wins.\n")
         f.write(f"# Written by python -m paper_2401_00710_amd.autotune on {device_name}, "
                 f"{time.strftime('%Y-%m-%d')}.\n")

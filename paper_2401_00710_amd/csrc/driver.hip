@@ -258,10 +258,11 @@ static uint32_t cutoff_for(int kb, bool hv, int req) {
 // ---------------------------------------------------------------- tuning
 // Rows of the tuning table: key bytes, value bytes, segmented (0/1), a range
 // [lo, hi] of floor(log2 n), and the parameters chosen for it (digit bits,
-// base-case cutoff, scatter tile shape; 0 = automatic).  The first matching
-// row wins.
+// base-case cutoff, scatter tile shape, digit bits of the levels below the
+// root; 0 = automatic, a missing last column is 0).  The first matching row
+// wins.
 struct TuneRow {
-  int kb, vb, seg, lo, hi, digit_bits, cutoff, tile;
+  int kb, vb, seg, lo, hi, digit_bits, cutoff, tile, digit_bits_below;
 };
 
 static std::string lib_dir() {
@@ -285,8 +286,9 @@ static const std::vector<TuneRow>& tune_table() {
     while (fgets(line, sizeof(line), f)) {
       if (line[0] == '#') continue;
       TuneRow t;
-      if (sscanf(line, "%d %d %d %d %d %d %d %d", &t.kb, &t.vb, &t.seg, &t.lo, &t.hi, &t.digit_bits, &t.cutoff,
-                 &t.tile) == 8)
+      t.digit_bits_below = 0;
+      if (sscanf(line, "%d %d %d %d %d %d %d %d %d", &t.kb, &t.vb, &t.seg, &t.lo, &t.hi, &t.digit_bits, &t.cutoff,
+                 &t.tile, &t.digit_bits_below) >= 8)
         r.push_back(t);
     }
     fclose(f);
@@ -296,7 +298,7 @@ static const std::vector<TuneRow>& tune_table() {
 }
 
 struct Tuned {
-  int digit_bits, cutoff, tile;
+  int digit_bits, cutoff, tile, digit_bits_below;
 };
 
 static Tuned tuned_params(int kb, int vb, bool seg, size_t n) {
@@ -304,13 +306,14 @@ static Tuned tuned_params(int kb, int vb, bool seg, size_t n) {
   while (lg < 63 && (2ull << lg) <= n) ++lg;
   for (const TuneRow& t : tune_table())
     if (t.kb == kb && t.vb == vb && t.seg == (seg ? 1 : 0) && lg >= t.lo && lg <= t.hi)
-      return Tuned{t.digit_bits, t.cutoff, t.tile};
-  return Tuned{0, 0, 0};
+      return Tuned{t.digit_bits, t.cutoff, t.tile, t.digit_bits_below};
+  return Tuned{0, 0, 0, 0};
 }
 
 // Resolved parameters of one call.
 struct Params {
-  int gover;        // digit-bit override (0 = automatic)
+  int gover;        // digit-bit override of the roots (0 = automatic)
+  int gbelow;       // ... of the subproblems below them (0 = automatic)
   uint32_t cutoff;  // base-case threshold
   int tile;         // scatter tile shape (LevelArgs::tile)
 };
@@ -319,15 +322,18 @@ template <typename K, typename V>
 static Params resolve_params(const SortJob<K, V>& J) {
   constexpr bool HV = HasVal<V>::value;
   const dtsort_opts& o = J.o;
-  int gover = o.digit_bits, creq = o.lds_cutoff, tile = o.tile_shape;
+  int gover = o.digit_bits, creq = o.lds_cutoff, tile = o.tile_shape, gbelow = o.digit_bits_below;
   if (o.tuned) {
     const Tuned tp = tuned_params((int)sizeof(K), HV ? (int)sizeof(V) : 0, J.seg != nullptr, J.n);
+    // the table's width below the root only where the caller left both widths open
+    if (gbelow <= 0 && gover <= 0) gbelow = tp.digit_bits_below;
     if (gover <= 0) gover = tp.digit_bits;
     if (creq <= 0) creq = tp.cutoff;
     if (tile <= 0) tile = tp.tile;
   }
   Params p;
   p.gover = gover;
+  p.gbelow = gbelow > 0 ? gbelow : gover;
   p.cutoff = cutoff_for((int)sizeof(K), HV, creq);
   p.tile = tile > 0 ? tile - 1 : 0;
   return p;
@@ -631,12 +637,15 @@ static int run_sort(Ctx* c, SortJob<K, V>& J, hipStream_t s, dtsort_stats* stats
   }
 
   // ---- levels
+  // the roots' children and every later subproblem take the width below the root
+  a.g_override = P.gbelow;
   int L = 0;
   for (; n_tasks > 0; ++L) {
     if (L >= MAX_LEVELS) return fail(DTSORT_EINTERNAL, "recursion deeper than expected");
-    // (levels below a learned root: its children's width a.g_learned_child is
-    // at most LEARN_GAMMA <= plan_gamma of any size, or the caller's width)
-    const int gmax = plan_gamma(max_size, gover);
+    // the widest digit of the level's tasks (below a learned root: its
+    // children's width a.g_learned_child)
+    int gmax = plan_gamma(max_size, L == 0 ? gover : P.gbelow);
+    if (learned && L >= 1) gmax = std::max(gmax, a.g_learned_child);
     // chunk: a multiple of 8192 records aiming at ~2048 units per level (the
     // prep kernel derives the same value when it is left 0)
     uint64_t chunk = (total + 2047) / 2048;
@@ -793,7 +802,8 @@ template <typename K, typename V>
 static GPlan graph_plan(const SortJob<K, V>& J, const Params& P, int levels = 0) {
   GPlan g;
   const uint64_t n = std::max<uint64_t>(J.n, 2);
-  g.gmax = plan_gamma((uint32_t)std::min<uint64_t>(n, 0xFFFFFFFFu), P.gover);
+  const uint32_t n32 = (uint32_t)std::min<uint64_t>(n, 0xFFFFFFFFu);
+  g.gmax = std::max(plan_gamma(n32, P.gover), plan_gamma(n32, P.gbelow));  // every recorded level's widest digit
   g.cutoff = P.cutoff;
   // Level bound: a task whose keys differ in at most gmin bits is the last of
   // its branch (one plain digit).  Otherwise its light children have at least
@@ -804,7 +814,8 @@ static GPlan graph_plan(const SortJob<K, V>& J, const Params& P, int levels = 0)
   // occurs (one per digit); tasks still open after them (only below
   // overflow buckets, which hold the few keys above a sample's maximum) are
   // finished by one workgroup each.
-  const int gmin = P.gover > 0 ? std::max(1, std::min(P.gover, GMAX)) : 8;
+  auto narrowest = [](int gw) { return gw > 0 ? std::max(1, std::min(gw, GMAX)) : 8; };
+  const int gmin = std::min(narrowest(P.gover), narrowest(P.gbelow));
   const int kb = J.key_bits;
   g.levels = std::min(MAX_LEVELS, kb <= gmin ? 1 : (kb - gmin + gmin - 1) / gmin + 1);
   if (levels > 0) g.levels = std::min(MAX_LEVELS, levels);
@@ -945,6 +956,7 @@ static void graph_enqueue(Work& W, const GPlan& g, const SortJob<K, V>& J, const
   } else {
     launch_root<K>((Task*)W.tasks[0].p, dctr, J.n, J.key_bits, plan_gamma((uint32_t)J.n, P.gover), s);
   }
+  a.g_override = P.gbelow;  // the roots' children and every later subproblem
   for (int L = 0; L < g.levels; ++L) {
     LevelKeep& K_ = W.lv[L];
     a.tasks = (Task*)W.tasks[L & 1].p;
@@ -997,12 +1009,12 @@ struct GraphKey {
   const uint64_t* seg;
   uint32_t n_seg;
   uint64_t seed;
-  int key_bits, mode, gover, tile, levels, ordered, merge_variant;
+  int key_bits, mode, gover, gbelow, tile, levels, ordered, merge_variant;
   uint32_t cutoff;
   bool operator==(const GraphKey& o) const {
     return kb == o.kb && vb == o.vb && k == o.k && v == o.v && ws == o.ws && n == o.n && seg == o.seg &&
            n_seg == o.n_seg && seed == o.seed && key_bits == o.key_bits && mode == o.mode && gover == o.gover &&
-           tile == o.tile && levels == o.levels && cutoff == o.cutoff && ordered == o.ordered &&
+           gbelow == o.gbelow && tile == o.tile && levels == o.levels && cutoff == o.cutoff && ordered == o.ordered &&
            merge_variant == o.merge_variant;
   }
 };
@@ -1044,6 +1056,7 @@ static int graph_sort(Ctx* c, SortJob<K, V>& J, void* user_ws, hipStream_t s, dt
   key.key_bits = J.key_bits;
   key.mode = J.o.mode;
   key.gover = P.gover;
+  key.gbelow = P.gbelow;
   key.tile = P.tile;
   key.ordered = J.o.ordered_ranks != 0;
   key.merge_variant = J.o.merge_variant;
@@ -1172,6 +1185,8 @@ static int prepare_job(K* keys, V* vals, size_t n, const uint64_t* seg, size_t n
   if (key_bits > kbits) return fail(DTSORT_EINVAL, "key_bits larger than the key width");
   if (o.mode < 0 || o.mode > 2) return fail(DTSORT_EINVAL, "unknown mode");
   if (o.digit_bits < 0 || o.digit_bits > GMAX) return fail(DTSORT_EINVAL, "digit_bits out of range");
+  if (o.digit_bits_below < 0 || o.digit_bits_below > GMAX)
+    return fail(DTSORT_EINVAL, "digit_bits_below out of range");
   if (o.tile_shape < 0 || o.tile_shape > 6) return fail(DTSORT_EINVAL, "tile_shape out of range");
   if (o.merge_variant < MV_GATHER || o.merge_variant > MV_SPLIT) return fail(DTSORT_EINVAL, "unknown merge_variant");
   if (o.learned_judge < 0 || o.learned_judge > 1) return fail(DTSORT_EINVAL, "unknown learned_judge");

@@ -100,7 +100,9 @@ def test_host_argument_checks():
     lib.dtsort_default_opts(C.byref(bad))
     bad.digit_bits = 11
     assert lib.dtsort_u32(C.c_void_p(4096), 10, C.byref(bad), None) == L.EINVAL
-    bad.digit_bits, bad.tile_shape = 0, 7
+    bad.digit_bits, bad.digit_bits_below = 0, 11
+    assert lib.dtsort_u32(C.c_void_p(4096), 10, C.byref(bad), None) == L.EINVAL
+    bad.digit_bits_below, bad.tile_shape = 0, 7
     assert lib.dtsort_u32(C.c_void_p(4096), 10, C.byref(bad), None) == L.EINVAL
     bad.tile_shape, bad.graph, bad.mode = 0, 1, L.MODE_LEARNED
     assert lib.dtsort_u32(C.c_void_p(4096), 10, C.byref(bad), None) == L.EINVAL
@@ -119,11 +121,11 @@ def test_tune_table_format():
         if line.startswith("#") or not line.strip():
             continue
         v = [int(x) for x in line.split()]
-        assert len(v) == 8, line
-        kb, vb, seg, lo, hi, g, cut, tile = v
+        assert len(v) == 9, line
+        kb, vb, seg, lo, hi, g, cut, tile, g_below = v
         assert kb in (4, 8) and vb in (0, 4, 8) and seg in (0, 1)
         assert 0 <= lo <= hi <= 63
-        assert 0 <= g <= 10 and 0 <= cut <= 16384 and 0 <= tile <= 6
+        assert 0 <= g <= 10 and 0 <= cut <= 16384 and 0 <= tile <= 6 and 0 <= g_below <= 10
         rows.append(v)
     # every layout the entry points take has a row
     keys = {(r[0], r[1], r[2]) for r in rows}
@@ -134,9 +136,13 @@ def test_tune_table_format():
 def test_autotune_table_writer(tmp_path):
     from paper_2401_00710_amd import autotune
     p = tmp_path / "t.txt"
-    autotune.write_table([(4, 0, 0, 0, 63, 9, 8192, 3)], str(p), "test")
+    autotune.write_table([(4, 0, 0, 0, 63, 9, 8192, 3, 9)], str(p), "test")
     lines = [x for x in open(p) if not x.startswith("#")]
-    assert lines == ["4 0 0 0 63 9 8192 3\n"]
+    assert lines == ["4 0 0 0 63 9 8192 3 9\n"]
+    # a table written before the last column reads with 0 there
+    q = tmp_path / "old.txt"
+    q.write_text("# old\n4 0 0 0 63 9 8192 3\n")
+    assert autotune.read_table(str(q)) == [(4, 0, 0, 0, 63, 9, 8192, 3, 0)]
 
 
 def test_noalloc_host_checks():

@@ -4,7 +4,8 @@ options, each result compared bit-exactly with the oracle's stable sort
 
 The per-option tests elsewhere vary one knob at a time; here every case draws
 all of them at once (digit width, base-case cutoff, scatter tile, merge
-variant, heavy-key detection on or off, ordered ranks, graph form), so that
+variant, heavy-key detection on or off, ordered ranks, graph form, digit
+width below the root), so that
 interactions between options are exercised too.  A case is fixed by its
 index: its parameters are printed before it runs and are the same in every
 process.
@@ -64,6 +65,7 @@ def _case(i):
         n=int(rs.choice(SIZES)),
         kind=str(rs.choice(KINDS)),
         digit_bits=int(rs.choice([0, 0, 2, 4, 7, 8, 9, 10])),
+        digit_bits_below=int(rs.choice([0, 0, 0, 3, 8, 9])),
         lds_cutoff=int(rs.choice([0, 0, 2, 50, 600, 5000, 20000])),
         tile_shape=int(rs.integers(0, 7)),
         merge_variant=int(rs.choice([dt.MERGE_GATHER, dt.MERGE_GATHER, dt.MERGE_PLMERGE, dt.MERGE_INPLACE,

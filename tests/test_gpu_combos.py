@@ -24,7 +24,7 @@ pytestmark = pytest.mark.gpu
 ENTRIES = ["u32", "u64", "pairs_u64", "pairs_u32", "seg", "seg_vals"]
 SIZES = [0, 1, 2, 7, 257, 1025, 4097, 8193, 16385, 32769, 65537, 123457, 200003]
 KINDS = ["uniform", "zipf", "equal", "two", "exp", "bexp", "max", "small_range", "sorted", "reversed"]
-N_CASES = 72
+N_CASES = 120
 
 
 def _keys(kind, n, wide, rs):

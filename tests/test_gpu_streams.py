@@ -111,3 +111,13 @@ def test_more_streams_than_contexts():
             dt.sort_u32(d)
             st.synchronize()
             assert np.array_equal(host_u32(d), np.sort(k)), i
+    # releasing every stream's cache, then sorting again, allocates afresh
+    torch.cuda.synchronize()
+    import paper_2401_00710_amd._lib as L
+    L.load().dtsort_release()
+    k = rs.integers(0, 2 ** 32, 123457, dtype=np.uint64).astype(np.uint32)
+    with torch.cuda.stream(streams[5]):
+        d = dev_u32(k)
+        dt.sort_u32(d)
+        streams[5].synchronize()
+    assert np.array_equal(host_u32(d), np.sort(k))

@@ -596,6 +596,7 @@ __global__ __launch_bounds__(256) void k_merge_gather(const Merge* m, const uint
   __shared__ uint32_t P[MAXH], S[MAXH], PRE[MAXH];
   __shared__ K HK[MAXH];
   __shared__ uint32_t tmp[5];
+  __shared__ uint32_t s_run[3];  // the unit's run: kind (0 mixed, 1 one heavy run, 2 one light stretch), index, offset
   const uint32_t n_units = min(*count, cap);
   for (uint32_t ui = blockIdx.x; ui < n_units; ui += gridDim.x) {
   const uint2 u = munits[ui];
@@ -619,9 +620,9 @@ __global__ __launch_bounds__(256) void k_merge_gather(const Merge* m, const uint
   const uint32_t qn = min((uint32_t)MERGE_TILE, zsize - q0);  // outputs of this unit
   const K* lk = bf.k[mg.b0_buf] + mg.zone_off;
   K* ok = bf.k[mg.out_buf] + mg.zone_off;
-  for (uint32_t qi = threadIdx.x; qi < qn; qi += 256) {
-    const uint32_t q = q0 + qi;
-    // largest i with P[i] <= q
+  // output q: lo = heavy runs starting at or before q; inside run lo - 1, or
+  // light record q - before
+  auto locate = [&](uint32_t q, uint32_t* lo_out, bool* heavy, uint32_t* hidx, uint32_t* before) {
     uint32_t lo = 0, n = mg.m;
     while (n > 0) {
       const uint32_t half = n >> 1;
@@ -632,17 +633,56 @@ __global__ __launch_bounds__(256) void k_merge_gather(const Merge* m, const uint
         n = half;
       }
     }
-    bool heavy = false;
-    uint32_t hidx = 0, before = 0;
+    *lo_out = lo;
+    *heavy = false;
+    *hidx = 0;
+    *before = 0;
     if (lo > 0) {
       const uint32_t i = lo - 1;
       if (q < P[i] + S[i]) {
-        heavy = true;
-        hidx = i;
+        *heavy = true;
+        *hidx = i;
       } else {
-        before = PRE[i] + S[i];
+        *before = PRE[i] + S[i];
       }
     }
+  };
+  // a unit inside one heavy run (a constant) or one light stretch (a shifted
+  // copy) needs no search per output: heavy keys fill most of a skewed zone
+  if (threadIdx.x == 0) {
+    uint32_t lo_a, lo_b, h_a, h_b, be_a, be_b;
+    bool hv_a, hv_b;
+    locate(q0, &lo_a, &hv_a, &h_a, &be_a);
+    locate(q0 + qn - 1u, &lo_b, &hv_b, &h_b, &be_b);
+    s_run[0] = (hv_a && hv_b && h_a == h_b) ? 1u : ((!hv_a && !hv_b && lo_a == lo_b) ? 2u : 0u);
+    s_run[1] = h_a;
+    s_run[2] = be_a;
+  }
+  __syncthreads();
+  const uint32_t kind = s_run[0];
+  if (kind == 1u) {
+    const uint32_t i = s_run[1];
+    const K hk = HK[i];
+    for (uint32_t qi = threadIdx.x; qi < qn; qi += 256) ok[q0 + qi] = hk;
+    if constexpr (HasVal<V>::value) {
+      V* ov = bf.v[mg.out_buf] + mg.zone_off;
+      const V* hv = bf.v[mg.hv_buf] + mg.zone_off + mg.b0 + PRE[i];
+      for (uint32_t qi = threadIdx.x; qi < qn; qi += 256) ov[q0 + qi] = hv[q0 + qi - P[i]];
+    }
+  } else if (kind == 2u) {
+    const uint32_t before = s_run[2];
+    for (uint32_t qi = threadIdx.x; qi < qn; qi += 256) ok[q0 + qi] = lk[q0 + qi - before];
+    if constexpr (HasVal<V>::value) {
+      V* ov = bf.v[mg.out_buf] + mg.zone_off;
+      const V* lv = bf.v[mg.b0_buf] + mg.zone_off;
+      for (uint32_t qi = threadIdx.x; qi < qn; qi += 256) ov[q0 + qi] = lv[q0 + qi - before];
+    }
+  }
+  for (uint32_t qi = threadIdx.x; kind == 0u && qi < qn; qi += 256) {
+    const uint32_t q = q0 + qi;
+    uint32_t lo, hidx, before;
+    bool heavy;
+    locate(q, &lo, &heavy, &hidx, &before);
     const uint32_t li = min(q - before, mg.b0 ? mg.b0 - 1u : 0u);  // in range by construction
     if (heavy) {
       ok[q] = HK[hidx];

@@ -270,3 +270,44 @@ def test_step_dtmerge(seed):
     assert st == 0
     assert np.array_equal(host_u64(ok), ek)
     assert np.array_equal(host_u64(ov), ev)
+
+
+# Zone layouts whose gather units (4096 outputs each) lie wholly inside one
+# heavy run, wholly inside one stretch of light records, or straddle a
+# boundary, with run ends on unit edges: the gather fills a unit inside a run
+# with the run's key and copies a unit inside a light stretch as one shifted
+# range, and searches the run starts per output only in straddling units.
+# Heavy keys are even and light keys odd, so none is equal.
+_RUN_LAYOUTS = {
+    "runs_on_unit_edges": (0, [(10, 4096), (20, 8192), (30, 4096)]),
+    "one_long_run_inside_light": (30000, [(2 ** 39, 50000)]),
+    "light_starts_on_unit_edge": (3 * 4096, [(2, 4095), (4, 1)]),
+    "runs_above_all_light": (10000, [(2 ** 42 + 2 * i, 12289 + 4096 * i) for i in range(5)]),
+    "light_between_long_runs": (9000, [(2, 9000), (2 ** 42, 4097)]),
+}
+
+
+@pytest.mark.parametrize("layout", sorted(_RUN_LAYOUTS))
+def test_step_dtmerge_runs(layout):
+    require_gpu()
+    lib = _lib()
+    nb0, runs = _RUN_LAYOUTS[layout]
+    rs = np.random.default_rng(seed_of("dtmerge_runs", layout))
+    heavy = np.array([h for h, _ in runs], np.uint64)
+    sizes = np.array([c for _, c in runs], np.uint32)
+    b0 = np.sort(rs.integers(0, 2 ** 40, nb0).astype(np.uint64) * np.uint64(2) + np.uint64(1))
+    b0v = rs.integers(0, 2 ** 63, nb0, dtype=np.uint64)
+    hv_list = [rs.integers(0, 2 ** 63, int(c), dtype=np.uint64) for c in sizes]
+    ek, ev = R.dtmerge_gather(b0, b0v, heavy, hv_list, sizes.astype(np.int64))
+    zs = ek.size
+    ok = torch.empty(zs, dtype=torch.int64, device="cuda")
+    ov = torch.empty(zs, dtype=torch.int64, device="cuda")
+    d_b0 = dev_u64(b0) if nb0 else torch.empty(1, dtype=torch.int64, device="cuda")
+    d_b0v = dev_u64(b0v) if nb0 else torch.empty(1, dtype=torch.int64, device="cuda")
+    d_hv = dev_u64(np.concatenate(hv_list))
+    say(f"dtmerge runs {layout}: b0={nb0} runs={[int(c) for c in sizes]}")
+    st = lib.dtsort_step_dtmerge_u64(d_b0.data_ptr(), d_b0v.data_ptr(), nb0, heavy.ctypes.data, sizes.ctypes.data,
+                                     len(runs), d_hv.data_ptr(), ok.data_ptr(), ov.data_ptr(), _stream())
+    assert st == 0
+    assert np.array_equal(host_u64(ok), ek)
+    assert np.array_equal(host_u64(ov), ev)

@@ -508,9 +508,12 @@ __global__ __launch_bounds__(T, (scatter_min_waves<T, ITEMS, (int)(sizeof(K) * (
         }
       }
       if constexpr (ATOM) {
+        // bucket (< 2^16) and rank in the tile (< 2^16) share a register:
+        // the 1024 x 16 tile is at the register limit
+        static_assert(TILE <= 65536 && NBMAX <= 65536, "bucket and rank fit 16 bits each");
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i)
-          pos[i] = (uint32_t)striped_index<T, ITEMS>(i) < tile_n ? atomicAdd(&tcnt[bk[i]], 1u) : 0u;
+          bk[i] = (uint32_t)striped_index<T, ITEMS>(i) < tile_n ? (bk[i] << 16) | atomicAdd(&tcnt[bk[i]], 1u) : 0u;
       }
 #pragma unroll
       for (int i = 0; i < ((RANK == RANK_PIPE || ATOM) ? 0 : ITEMS); ++i) {
@@ -616,10 +619,17 @@ __global__ __launch_bounds__(T, (scatter_min_waves<T, ITEMS, (int)(sizeof(K) * (
       for (int i = 0; i < ITEMS; ++i) {
         const uint32_t e = (uint32_t)striped_index<T, ITEMS>(i);
         if (e < tile_n) {
-          const uint32_t p = pos[i] + (ATOM ? tcnt[bk[i]] : crow[bk[i]]);
-          pos[i] = p;
-          stage[p] = kk[i];
-          stage_b[p] = (uint16_t)bk[i];
+          if constexpr (ATOM) {
+            const uint32_t b = bk[i] >> 16;
+            const uint32_t p = (bk[i] & 0xFFFFu) + tcnt[b];
+            stage[p] = kk[i];
+            stage_b[p] = (uint16_t)b;
+          } else {
+            const uint32_t p = pos[i] + crow[bk[i]];
+            pos[i] = p;
+            stage[p] = kk[i];
+            stage_b[p] = (uint16_t)bk[i];
+          }
         }
       }
       __syncthreads();

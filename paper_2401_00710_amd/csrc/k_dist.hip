@@ -174,8 +174,11 @@ __device__ inline void load_tables(const Task& t, const uint8_t* tab, uint32_t* 
 // Units with a grid stride; the workgroup's counts of a unit go to its
 // column of the task's count matrix.
 // SPLIT: tasks in the split bucket layout (bucket_of<K, true>).
+// At least 6 waves a SIMD (at most 80 VGPRs): three 512-thread workgroups
+// share a CU, which hides the LDS latency of the heavy-key lookups; 8 waves
+// would spill the 32-bit variants.
 template <typename K, int T, int ITEMS, int NBMAX, bool SPLIT = false>
-__global__ __launch_bounds__(T) void k_hist(LevelArgs a, const K* k0, const K* k1) {
+__global__ __launch_bounds__(T, 6) void k_hist(LevelArgs a, const K* k0, const K* k1) {
   constexpr int WAVES = T / WAVE;
   constexpr int GM = NBMAX <= NB8 ? 8 : (NBMAX <= NB9 ? 9 : GMAX);  // widest digit of this variant
   // two counter rows per wave on the <= 8-bit variants, for even and odd

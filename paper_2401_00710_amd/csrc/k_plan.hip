@@ -202,8 +202,16 @@ void launch_plan(const LevelArgs& a, const K* k0, const K* k1, int g_level_max, 
 // Base case: a stable radix sort in LDS of a subproblem of at most T*ITEMS
 // records, only over the bit range in which its keys differ.  With T = 64 a
 // workgroup holds SUB independent one-wave sorters, each with its own LDS.
+template <typename K, typename V, int T, int ITEMS, int RANKREQ, int SUB>
+constexpr int leaf_min_waves() {
+  // 4096 bare 32-bit keys, LDS-match ranks: 28 KB of LDS lets five
+  // workgroups share a CU, which takes at most 96 VGPRs (the other ranking
+  // modes would spill there)
+  return (sizeof(K) == 4 && !HasVal<V>::value && T * SUB == 256 && ITEMS == 16 && RANKREQ == RANK_LDS) ? 5 : 1;
+}
+
 template <typename K, typename V, int T, int ITEMS, int RANKREQ, int SUB = 1>
-__global__ __launch_bounds__(T* SUB) void k_leaf(const Leaf* items, const uint32_t* count, uint32_t cap,
+__global__ __launch_bounds__(T* SUB, (leaf_min_waves<K, V, T, ITEMS, RANKREQ, SUB>())) void k_leaf(const Leaf* items, const uint32_t* count, uint32_t cap,
                                                  Bufs<K, V> bf) {
   static_assert(SUB == 1 || T == WAVE, "several sorters per workgroup only for one-wave sorters");
   constexpr int N = T * ITEMS;
